@@ -1,0 +1,168 @@
+/*
+ * df.h - C ABI of the ladder dual-fermion hot path on one MI355X (gfx950).
+ *
+ * One outer iteration of the ladder dual-fermion method (paper Sec. 2.2):
+ *
+ *   df_dual_gf       dual Green's function G~ from the DMFT inputs g, Delta,
+ *                    the dispersion eps_k (eq. gd0) and the current dual
+ *                    self-energy (eq. dyson): G~ = G~0 / (1 - G~0 Sigma~)
+ *   df_bubble        dual bubble chi_{Om,nu}(q) = -(T/N) sum_k G~_{nu,k} G~_{nu+Om,k+q}
+ *                    (eq. dual_bubble) as FFT convolutions over the k-grid
+ *   df_ladder_solve  for every (channel, Om, q): Gamma = [1 - gamma chi]^-1 gamma
+ *                    (eqs. dual_ladder, lin_alg_inv), convergence-radius test and
+ *                    one-step fallback, and W = diag(Gamma) - diag(gamma chi gamma)/2
+ *   df_sigma         dual self-energy of eq. (sd) contracted through a second
+ *                    FFT convolution
+ *   df_iterate       the whole loop with linear mixing until Sigma~ converges
+ *
+ * Conventions
+ *   - Every array pointer in df_inst_t is a DEVICE pointer on the current HIP
+ *     device.  Complex numbers are interleaved (re, im) doubles.
+ *   - Fermionic window n in [-n_nu/2, n_nu/2), nu_n = (2n+1) pi / beta.
+ *     Bosonic window m in [-(n_om-1)/2, (n_om-1)/2], Om_m = 2 m pi / beta.
+ *     Arrays index the windows from 0 (index = n + n_nu/2, m + (n_om-1)/2).
+ *   - k-grid: k_j = 2 pi j / nk on each of the D axes; flat index in C order
+ *     of the D-dimensional array of shape (nk,)*D; N = nk^D.
+ *   - A propagator G~_{nu+Om} whose frequency leaves the window is zero.
+ *   - Channel 0 is the density channel gamma^d = gamma^uu + gamma^ud, channel 1
+ *     the magnetic channel gamma^m = gamma^uu - gamma^ud (eq. spin_symm).
+ *   - Inside the convergence radius <=> Re det(1 - gamma chi) > 0; outside (or
+ *     a singular matrix) the ladder takes one step, Gamma = gamma + gamma chi gamma,
+ *     and is re-tested on the next iteration.
+ *
+ * Ownership: the caller allocates every buffer, the workspace included (size
+ * it with df_workspace_size; it must be 256-byte aligned).  The library never
+ * allocates or frees caller memory; it keeps no state between calls apart
+ * from compiled kernels.  Calls are asynchronous on the given stream, except
+ * df_iterate which synchronises that stream to read back the convergence
+ * measure once per iteration.  Calls on distinct workspaces may run
+ * concurrently; two calls sharing a workspace must be ordered by the caller.
+ *
+ * Errors: argument errors are detected on the host and returned before any
+ * work is queued.  No exception crosses the ABI.
+ */
+#ifndef DF_H
+#define DF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DF_OK                0
+#define DF_E_INVAL          -1   /* null pointer, bad size, bad option          */
+#define DF_E_UNSUPPORTED    -2   /* shape outside what the kernels handle       */
+#define DF_E_WORKSPACE      -3   /* workspace missing, too small or misaligned  */
+#define DF_E_HIP            -4   /* a HIP runtime call failed                   */
+#define DF_E_NONFINITE      -5   /* Sigma~ became non-finite during df_iterate  */
+#define DF_E_NOT_CONVERGED  -6   /* max_iter reached; outputs hold the last iterate */
+#define DF_W_FALLBACK        1   /* success, but some ladders were outside the radius */
+
+/* per-(channel, Om, q) ladder status */
+#define DF_LADDER_OK         0
+#define DF_LADDER_FALLBACK   1
+#define DF_LADDER_SINGULAR   2
+
+/* ladder precision */
+#define DF_FP64              0   /* plain FP64 inversion                          */
+#define DF_FP32_REFINE       1   /* FP32 inversion + FP64 residual refinement     */
+
+typedef void *df_stream_t;      /* hipStream_t; NULL is the null stream */
+
+/*
+ * One problem instance.
+ *   D      lattice dimension, 1..3
+ *   nk     k-points per axis, a power of two in [4, 64]; N = nk^D <= 4096
+ *   n_nu   fermionic frequencies, even, 2..128
+ *   n_om   bosonic frequencies, odd, 1 <= n_om <= n_nu - 1
+ *   beta   inverse temperature, > 0
+ * Inputs (read only):
+ *   g, delta           [n_nu]              impurity g(nu) and hybridisation Delta(nu)
+ *   eps                [N]   (real)        dispersion eps_k
+ *   gamma_uu, gamma_ud [n_om][n_nu][n_nu]  impurity vertex gamma^{uu}, gamma^{ud}
+ *                                          indexed [m][n][n']
+ * State and outputs:
+ *   sigma        [n_nu][N]            dual self-energy Sigma~ (df_dual_gf input, NULL = 0;
+ *                                     df_iterate in/out)
+ *   gd           [n_nu][N]            dual Green's function G~
+ *   chi          [n_om][n_nu][N]      dual bubble chi[m][n][q]
+ *   w            [2][n_om][n_nu][N]   W^c_{m,n}(q) = Gamma_nn - (gamma chi gamma)_nn / 2
+ *   logdet       [2][n_om][N]         complex log det(1 - gamma chi), Im in (-pi, pi]
+ *   status       [2][n_om][N] (int8)  DF_LADDER_*
+ *   sigma_calc   [n_nu][N]            Sigma~ of eq. (sd) before mixing
+ * Which fields a call reads or writes is stated at each entry point.
+ */
+typedef struct {
+    int32_t D, nk, n_nu, n_om;
+    double beta;
+    const double *g, *delta, *eps, *gamma_uu, *gamma_ud;
+    double *sigma, *gd, *chi, *w, *logdet, *sigma_calc;
+    int8_t *status;
+} df_inst_t;
+
+/*
+ * Options.
+ *   prec        DF_FP64 or DF_FP32_REFINE
+ *   max_refine  refinement steps of the FP32 path (1..4); ignored for DF_FP64
+ *   mix         weight alpha of the new Sigma~ in the linear mixing, (0, 1]
+ *   tol         df_iterate stops once ||Sigma_new - Sigma_old||_F / ||Sigma_new||_F < tol
+ *               (every instance); tol <= 0 runs exactly max_iter iterations
+ *   max_iter    iteration limit of df_iterate, >= 1
+ *   use_graph   nonzero: df_iterate captures one iteration in a hipGraph and replays it
+ */
+typedef struct {
+    int32_t prec;
+    int32_t max_refine;
+    double mix;
+    double tol;
+    int32_t max_iter;
+    int32_t use_graph;
+} df_opts_t;
+
+/* Workspace bytes needed by any entry point for these instances and options. */
+int df_workspace_size(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
+                      size_t *bytes);
+
+/* eq. (gd0), eq. (dyson).  Reads g, delta, eps, sigma (NULL = zero).  Writes gd. */
+int df_dual_gf(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
+               df_stream_t stream);
+
+/* eq. (dual_bubble).  Reads gd.  Writes chi. */
+int df_bubble(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
+              df_stream_t stream);
+
+/* eqs. (spin_symm), (dual_ladder), (lin_alg_inv) and the radius test; Gamma^(2) of
+ * eq. (sd).  Reads gamma_uu, gamma_ud, chi.  Writes w and, when non-NULL, logdet
+ * and status.  opts may be NULL (DF_FP64).  Returns DF_OK; the per-ladder
+ * outcome is in status. */
+int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
+                    void *ws, size_t ws_bytes, df_stream_t stream);
+
+/* eq. (sd).  Reads w, gd.  Writes sigma_calc. */
+int df_sigma(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
+             df_stream_t stream);
+
+/* The self-consistency loop.  Reads the inputs and sigma (the start value, e.g.
+ * zero or a warm start); writes the final sigma and gd, and the last iteration's
+ * chi, w, logdet, status, sigma_calc wherever those pointers are non-NULL.
+ * iters_out (host, may be NULL) receives the iterations done; diff_out (host,
+ * may be NULL) receives n_inst final diffs.  Returns DF_OK, DF_W_FALLBACK (some
+ * ladder of the last iteration fell back), DF_E_NOT_CONVERGED or DF_E_NONFINITE. */
+int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
+               int32_t *iters_out, double *diff_out, void *ws, size_t ws_bytes,
+               df_stream_t stream);
+
+/* Static description of a status code. */
+const char *df_strerror(int code);
+
+/* ABI version (major * 100 + minor). */
+int df_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DF_H */

@@ -1,0 +1,82 @@
+// Kernel argument blocks and launcher declarations of libdf (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "df_device.hpp"
+
+namespace df {
+
+struct DualGfArgs {
+    Grid grid;
+    int n_nu;
+    const double *g, *delta, *eps;   // inputs (unused with from_gd)
+    const double *sigma;             // may be null (Sigma~ = 0)
+    const double *gd_in;             // with from_gd: G~ to transform
+    double *gd_out;                  // may be null
+    double *gr_out;                  // may be null: [n_nu][N] inverse FFT of G~
+    int from_gd;
+};
+
+struct BubbleArgs {
+    Grid grid;
+    int n_nu, n_om;
+    double beta;
+    const double *gr;                // [n_nu][N]
+    double *chi;                     // [n_om][n_nu][N]
+};
+
+struct SigmaArgs {
+    Grid grid;
+    int n_nu, n_om;
+    int chunk_len, n_chunks;
+    double beta;
+    const double *w;                 // [2][n_om][n_nu][N]
+    const double *gr;                // [n_nu][N]
+    double *part;                    // [n_chunks][n_nu][N]
+};
+
+struct ReduceMixArgs {
+    size_t count;                    // n_nu * N complex elements
+    int n_chunks;
+    double alpha;
+    const double *part;
+    double *sigma_calc;              // may be null
+    double *sigma;                   // may be null: no mixing
+    double *norm_part;               // [gridDim][2]
+};
+
+struct GammaPrepArgs {
+    int n_nu, n_om;
+    const double *guu, *gud;
+    double *gdm;                     // [2][n_om][n_nu][n_nu]
+    double *pdm;                     // [2][n_om][n_nu][n_nu]
+};
+
+struct LadderArgs {
+    const double *gdm;               // [2][n_om][n_nu][n_nu]
+    const double *pdm;               // [2][n_om][n_nu][n_nu]
+    const double *chi;               // [n_om][n_nu][N]
+    double *w;                       // [2][n_om][n_nu][N]
+    double *logdet;                  // [2][n_om][N] or null
+    int8_t *status;                  // [2][n_om][N] or null
+    int n_nu, n_om, N;
+    int item0, n_items;              // items are (c, m, q), q fastest
+    int *fallback_count;             // may be null: atomically counts status != 0
+};
+
+hipError_t launch_dual_gf(const DualGfArgs &a, hipStream_t s);
+hipError_t launch_bubble(const BubbleArgs &a, hipStream_t s);
+hipError_t launch_sigma_part(const SigmaArgs &a, hipStream_t s);
+hipError_t launch_reduce_mix(const ReduceMixArgs &a, int blocks, hipStream_t s);
+hipError_t launch_norm_final(const double *part, int n_part, double *out, hipStream_t s);
+hipError_t launch_gamma_prep(const GammaPrepArgs &a, hipStream_t s);
+hipError_t set_fft_lds_limits();
+
+// padded ladder size for n_nu, 0 if unsupported
+int ladder_padded_size(int n_nu);
+hipError_t launch_ladder_fp64(const LadderArgs &a, hipStream_t s);
+
+}  // namespace df

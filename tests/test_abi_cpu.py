@@ -1,0 +1,107 @@
+"""Host-side checks of the C ABI: symbols, struct layout, argument validation.
+
+No GPU is needed: every call below fails validation before any HIP work.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1507_00895_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "df.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(df_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    decl = declared_functions()
+    assert set(decl) == set(B.EXPORTED)
+    for name in decl:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (df_\w+)", out))
+    assert set(decl) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text('''
+#include <stdio.h>
+#include <stddef.h>
+#include "df.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(df_inst_t), offsetof(df_inst_t, beta),
+         offsetof(df_inst_t, g), offsetof(df_inst_t, status), sizeof(df_opts_t),
+         offsetof(df_opts_t, max_iter));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals == [ctypes.sizeof(B.DfInst), B.DfInst.beta.offset, B.DfInst.g.offset,
+                    B.DfInst.status.offset, ctypes.sizeof(B.DfOpts), B.DfOpts.max_iter.offset]
+
+
+def _inst(**kw):
+    base = dict(D=2, nk=8, n_nu=16, n_om=1, beta=10.0)
+    base.update(kw)
+    fake = 0x1000
+    return B.DfInst(base["D"], base["nk"], base["n_nu"], base["n_om"], base["beta"],
+                    *([fake] * 11), fake)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_om=2), B.DF_E_INVAL),            # even bosonic count
+    (dict(n_nu=15), B.DF_E_INVAL),           # odd fermionic count
+    (dict(n_om=17), B.DF_E_INVAL),           # n_om > n_nu - 1
+    (dict(nk=12), B.DF_E_UNSUPPORTED),       # not a power of two
+    (dict(D=4), B.DF_E_UNSUPPORTED),
+    (dict(D=3, nk=32), B.DF_E_UNSUPPORTED),  # N = 32768 > 4096
+    (dict(n_nu=130, n_om=3), B.DF_E_UNSUPPORTED),
+    (dict(beta=0.0), B.DF_E_INVAL),
+])
+def test_workspace_size_rejects_bad_shapes(kw, code):
+    lib = B.load()
+    arr = (B.DfInst * 1)(_inst(**kw))
+    n = ctypes.c_size_t(0)
+    assert lib.df_workspace_size(arr, 1, None, ctypes.byref(n)) == code
+
+
+def test_workspace_size_and_validation_order():
+    lib = B.load()
+    arr = (B.DfInst * 1)(_inst())
+    n = ctypes.c_size_t(0)
+    assert lib.df_workspace_size(arr, 1, None, ctypes.byref(n)) == B.DF_OK
+    assert n.value > 0 and n.value % 256 == 0
+    # null / misaligned / short workspace is refused before any device work
+    assert lib.df_dual_gf(arr, 1, None, n.value, None) == B.DF_E_WORKSPACE
+    assert lib.df_bubble(arr, 1, 0x1001, n.value, None) == B.DF_E_WORKSPACE
+    assert lib.df_sigma(arr, 1, 0x1000, n.value - 256, None) == B.DF_E_WORKSPACE
+    assert lib.df_dual_gf(arr, 0, 0x1000, n.value, None) == B.DF_E_INVAL
+    bad = B.make_opts(mix=0.0)
+    assert lib.df_iterate(arr, 1, ctypes.byref(bad), None, None, 0x1000, n.value, None) == B.DF_E_INVAL
+    bad = B.make_opts(prec=7)
+    assert lib.df_ladder_solve(arr, 1, ctypes.byref(bad), 0x1000, n.value, None) == B.DF_E_INVAL
+    assert B.df_strerror(B.DF_E_WORKSPACE).startswith("workspace")
+    assert B.df_version() >= 100
+
+
+def test_workspace_grows_with_instances():
+    lib = B.load()
+    one = (B.DfInst * 1)(_inst())
+    two = (B.DfInst * 2)(_inst(), _inst(D=3, nk=4, n_nu=32, n_om=5))
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.df_workspace_size(one, 1, None, ctypes.byref(a)) == 0
+    assert lib.df_workspace_size(two, 2, None, ctypes.byref(b)) == 0
+    assert b.value > a.value

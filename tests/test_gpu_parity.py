@@ -1,0 +1,193 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every step is fed the same inputs on both sides, so each comparison isolates
+one kernel; the loop tests compare whole iterations.  The error metric is
+max|X - X_ref| / max|X_ref| per array; the FP64 path must stay within 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle import df_oracle as O
+from paper_1507_00895_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def rel(x, ref):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    den = np.abs(ref).max()
+    return float(np.abs(x - ref).max() / den) if den > 0 else float(np.abs(x).max())
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1507_00895_amd import binding as B
+    B.load()
+    return torch
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+# (D, nk, n_nu, n_om, beta, U, t)
+SHAPES = [
+    (2, 8, 16, 1, 10.0, 2.0, 0.1),      # the small 2D workload
+    (2, 8, 16, 5, 10.0, 2.0, 0.1),
+    (2, 4, 14, 3, 5.0, 2.0, 0.2),       # smallest grid, ragged n_nu (padded to 16)
+    (1, 64, 20, 7, 10.0, 2.0, 0.1),     # 1D, ragged n_nu (padded to 32)
+    (2, 16, 48, 9, 10.0, 2.0, 0.1),
+    (2, 32, 50, 5, 20.0, 2.0, 0.1),     # ragged n_nu (padded to 64)
+    (3, 8, 64, 7, 20.0, 2.0, 0.1),
+    (3, 16, 96, 3, 15.0, 3.0, I.T_REMAP_3D),
+    (2, 16, 128, 3, 10.0, 2.0, 0.1),
+    (2, 64, 32, 3, 10.0, 2.0, 0.1),     # largest 2D grid
+]
+
+
+def ids(s):
+    return "D{}nk{}nu{}om{}".format(*s[:4])
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[ids(s) for s in SHAPES])
+def test_step_parity(torch_dev, shape):
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    D, nk, n_nu, n_om, beta, U, t = shape
+    p = I.atomic_limit_problem(D, nk, n_nu, n_om, beta, U, t)
+    inst = B.make_instance(p)
+    ws = B.workspace([inst])
+    N = p.N
+    # a non-zero dual self-energy exercises the Dyson step
+    S = 1e-3 * I.random_complex((n_nu, N), seed=7)
+    inst.sigma.copy_(torch.as_tensor(S))
+    B.df_dual_gf([inst], ws)
+    B.df_bubble([inst], ws)
+    B.df_ladder_solve([inst], ws)
+    B.df_sigma([inst], ws)
+    torch.cuda.synchronize()
+
+    G0 = O.dual_gf0(p.g, p.delta, p.eps)
+    G_ref = O.dual_gf(G0, S)
+    gd = host(inst.gd)
+    assert rel(gd, G_ref) <= TOL64
+
+    chi = host(inst.chi)
+    assert rel(chi, O.bubble_fft(gd, D, nk, n_om, beta)) <= TOL64
+
+    gam = O.spin_channels(p.gamma_uu, p.gamma_ud)
+    lr = O.ladder(gam, chi)
+    assert np.array_equal(host(inst.status), lr.status)
+    assert rel(host(inst.w), lr.W) <= TOL64
+    ld = host(inst.logdet)
+    assert np.abs(ld.real - lr.logdet.real).max() <= 1e-11
+    assert np.abs(np.exp(1j * ld.imag) - np.exp(1j * lr.logdet.imag)).max() <= 1e-11
+
+    W = host(inst.w)
+    assert rel(host(inst.sigma_calc), O.sigma_fft(W, gd, D, nk, beta)) <= TOL64
+
+
+def test_iterate_small_workload_ten_iterations(torch_dev):
+    """2D 8x8, n_nu 16, Omega = 0, U = 2, beta = 10, 10 iterations, mixing 0.5."""
+    from paper_1507_00895_amd import binding as B
+    p = I.workload_small()[0]
+    inst = B.make_instance(p)
+    ws = B.workspace([inst])
+    code, iters, diffs = B.df_iterate([inst], ws, B.make_opts(mix=0.5, tol=0.0, max_iter=10))
+    assert iters == 10
+    r = O.iterate(p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta, p.n_om,
+                  alpha=0.5, max_iter=10)
+    assert rel(host(inst.sigma), r.sigma) <= TOL64
+    assert rel(host(inst.gd), r.G) <= TOL64
+    assert abs(diffs[0] - r.diff) <= 1e-10 * r.diff
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_iterate_converges_like_oracle(torch_dev, use_graph):
+    """3D 4^3 lattice, several Omega: run both sides to tol 1e-11."""
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    p = I.atomic_limit_problem(3, 4, 16, 5, 8.0, 2.0, 0.12)
+    inst = B.make_instance(p)
+    ws = B.workspace([inst])
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        code, iters, diffs = B.df_iterate([inst], ws, B.make_opts(mix=0.5, tol=1e-11, max_iter=200,
+                                                                   use_graph=use_graph), stream=s.cuda_stream)
+    s.synchronize()
+    r = O.iterate(p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta, p.n_om,
+                  alpha=0.5, tol=1e-11, max_iter=200)
+    assert code == B.DF_OK
+    assert abs(iters - r.iters) <= 1
+    assert rel(host(inst.sigma), r.sigma) <= 1e-10
+
+
+def test_graph_replay_matches_eager(torch_dev):
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    p = I.atomic_limit_problem(2, 16, 32, 7, 10.0, 2.0, 0.1)
+    out = []
+    for g in (0, 1):
+        inst = B.make_instance(p)
+        ws = B.workspace([inst])
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        B.df_iterate([inst], ws, B.make_opts(mix=0.5, max_iter=6, use_graph=g), stream=s.cuda_stream)
+        s.synchronize()
+        out.append(host(inst.sigma))
+    assert np.array_equal(out[0], out[1])
+
+
+def test_fallback_matches_oracle(torch_dev):
+    """Outside the convergence radius the one-step ladder is used and flagged."""
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    p = I.atomic_limit_problem(2, 8, 16, 1, 10.0, 2.0, 0.3)
+    inst = B.make_instance(p)
+    ws = B.workspace([inst])
+    B.df_dual_gf([inst], ws)
+    B.df_bubble([inst], ws)
+    B.df_ladder_solve([inst], ws)
+    torch.cuda.synchronize()
+    gam = O.spin_channels(p.gamma_uu, p.gamma_ud)
+    lr = O.ladder(gam, host(inst.chi))
+    st = host(inst.status)
+    assert (st == 1).any()
+    assert np.array_equal(st, lr.status)
+    assert rel(host(inst.w), lr.W) <= TOL64
+    code, iters, _ = B.df_iterate([inst], ws, B.make_opts(mix=0.5, max_iter=2))
+    assert code == B.DF_W_FALLBACK
+
+
+def test_zero_vertex_gives_zero_sigma(torch_dev):
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    p = I.workload_small()[0]
+    p.gamma_uu = np.zeros_like(p.gamma_uu)
+    p.gamma_ud = np.zeros_like(p.gamma_ud)
+    inst = B.make_instance(p)
+    ws = B.workspace([inst])
+    code, iters, diffs = B.df_iterate([inst], ws, B.make_opts(mix=0.5, max_iter=3))
+    assert torch.count_nonzero(inst.sigma).item() == 0
+    assert diffs[0] == 0.0
+
+
+def test_multi_instance_matches_single(torch_dev):
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    probs = [I.atomic_limit_problem(2, 8, 16, 3, 10.0, 2.0, 0.1),
+             I.atomic_limit_problem(3, 4, 32, 5, 8.0, 3.0, 0.12),
+             I.atomic_limit_problem(2, 16, 64, 7, 20.0, 1.0, 0.1)]
+    insts = [B.make_instance(p) for p in probs]
+    ws = B.workspace(insts)
+    B.df_iterate(insts, ws, B.make_opts(mix=0.5, max_iter=4))
+    for p, x in zip(probs, insts):
+        r = O.iterate(p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta, p.n_om,
+                      alpha=0.5, max_iter=4)
+        assert rel(host(x.sigma), r.sigma) <= TOL64
