@@ -79,9 +79,21 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
             }
         }
     }
+    // t_i: reduce over the TC consecutive lanes that share row i
+#pragma unroll
+    for (int off = TC / 2; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int ai = 0; ai < BR; ++ai) {
+            tpart[ai].re += __shfl_xor(tpart[ai].re, off, 64);
+            tpart[ai].im += __shfl_xor(tpart[ai].im, off, 64);
+        }
+    }
     if (tc == 0) {
 #pragma unroll
-        for (int ai = 0; ai < BR; ++ai) colbuf[0][tr + TR * ai] = A[ai][0];
+        for (int ai = 0; ai < BR; ++ai) {
+            colbuf[0][tr + TR * ai] = A[ai][0];
+            tv[tr + TR * ai] = tpart[ai];
+        }
     }
     __syncthreads();
 
@@ -205,8 +217,8 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
     __syncthreads();
     const int stt = s_status;
 
-    // ---- Gamma_nn and t_n: partial sums over this thread's columns, then
-    //      a reduction over the TC consecutive lanes sharing the rows
+    // ---- Gamma_nn: partial sums over this thread's columns, then a
+    //      reduction over the TC consecutive lanes sharing the rows
     cd ypart[BR];
 #pragma unroll
     for (int ai = 0; ai < BR; ++ai) {
@@ -229,8 +241,6 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
         for (int ai = 0; ai < BR; ++ai) {
             ypart[ai].re += __shfl_xor(ypart[ai].re, off, 64);
             ypart[ai].im += __shfl_xor(ypart[ai].im, off, 64);
-            tpart[ai].re += __shfl_xor(tpart[ai].re, off, 64);
-            tpart[ai].im += __shfl_xor(tpart[ai].im, off, 64);
         }
     }
     if (tc == 0) {
@@ -238,7 +248,6 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
         for (int ai = 0; ai < BR; ++ai) {
             const int i = tr + TR * ai;
             yv[rowstep[i]] = ypart[ai];
-            tv[i] = tpart[ai];
         }
     }
     __syncthreads();
@@ -286,7 +295,7 @@ hipError_t launch_ladder_fp64(const LadderArgs &a, hipStream_t s) {
         case 32: return launch_one<32, 8, 8>(a, s);
         case 48: return launch_one<48, 16, 16>(a, s);
         case 64: return launch_one<64, 16, 16>(a, s);
-        case 96: return launch_one<96, 16, 16>(a, s);
+        case 96: return launch_one<96, 32, 16>(a, s);
         case 128: return launch_one<128, 32, 16>(a, s);
         default: return hipErrorInvalidValue;
     }
