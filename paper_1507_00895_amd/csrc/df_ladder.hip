@@ -19,7 +19,18 @@
 // log det D = sum_k log(pivot_k) + i pi * parity(sigma).
 #include "df_internal.hpp"
 
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_max_u32(unsigned int);
+
 namespace df {
+
+// Pivot-search key: the magnitude rounded to FP32 (whose bit pattern orders
+// like the value for non-negative numbers) with its low 8 bits replaced by
+// 255 - row, so that the unsigned maximum picks the largest magnitude and,
+// among equal magnitudes, the lowest row.  Rows already pivoted get key 0.
+__device__ __forceinline__ unsigned pivot_key(double mag, int row) {
+    const unsigned bits = __float_as_uint((float)mag);
+    return (bits & 0xFFFFFF00u) | (unsigned)(255 - row);
+}
 
 template <int NP, int TR, int TC>
 __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
@@ -104,31 +115,21 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
         for (int tcol = 0; tcol < TC; ++tcol) {
             const int k = kk * TC + tcol;
             const cd *col = colbuf[k & 1];
-            // arg-max of |re| + |im| over rows not yet pivoted (lowest index on ties)
-            double best = -1.0;
-            int bi = lane;
-            if (lane < NP && !used0) best = cabs1(col[lane]);
+            // arg-max of |re| + |im| over rows not yet pivoted (lowest index on
+            // ties), as one wave-wide unsigned max of packed (magnitude, index) keys
+            unsigned key = 0u;
+            if (lane < NP && !used0) key = pivot_key(cabs1(col[lane]), lane);
             if (NP > 64 && lane + 64 < NP && !used1) {
-                const double v = cabs1(col[lane + 64]);
-                if (v > best) {
-                    best = v;
-                    bi = lane + 64;
-                }
+                const unsigned k2 = pivot_key(cabs1(col[lane + 64]), lane + 64);
+                key = k2 > key ? k2 : key;
             }
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-            const int p = __builtin_amdgcn_readfirstlane(bi);
+            const int p = 255 - (int)(__ockl_wfred_max_u32(key) & 255u);
             if (p == lane) used0 = true;
             if (p == lane + 64) used1 = true;
             const cd piv = col[p];
-            const cd ip = recip(piv);
+            // 1/piv with one division (|piv|^2 cannot overflow for these matrices)
+            const double inv2 = 1.0 / fma(piv.re, piv.re, piv.im * piv.im);
+            const cd ip = {piv.re * inv2, -piv.im * inv2};
             const int trp = p % TR;
             const int ap = p / TR;
             if (tr == trp) {
