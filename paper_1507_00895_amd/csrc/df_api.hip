@@ -1,6 +1,7 @@
 // C ABI of libdf: argument validation, workspace layout, launch sequencing,
 // the self-consistency loop and its optional hipGraph capture.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <vector>
@@ -57,7 +58,7 @@ int check_inst(const df_inst_t &p, Shape *s) {
 
 // Per-instance workspace regions (byte offsets from the instance base).
 struct Layout {
-    size_t gr, gdm, pdm, part, norm, diff, count, gd, chi, w, sc, total;
+    size_t gr, gdm, pdm, gtr, queue, part, norm, diff, count, gd, chi, w, sc, total;
 };
 
 Layout layout_of(const Shape &s) {
@@ -73,10 +74,12 @@ Layout layout_of(const Shape &s) {
     L.gr = take(fld);
     L.gdm = take(2 * (size_t)s.n_om * s.n_nu * s.n_nu * cdb);
     L.pdm = take(2 * (size_t)s.n_om * s.n_nu * s.n_nu * cdb);
+    L.gtr = take(2 * (size_t)s.n_om * s.n_nu * s.n_nu * cdb);
+    L.queue = take(2 * (size_t)s.n_om * s.N * sizeof(int));
     L.part = take((size_t)s.n_chunks * fld);
     L.norm = take((size_t)kMixBlocks * 2 * sizeof(double));
     L.diff = take(2 * sizeof(double));
-    L.count = take(sizeof(int));
+    L.count = take(2 * sizeof(int));   // [0] ladders outside the radius, [1] queue length
     L.gd = take(fld);
     L.chi = take((size_t)s.n_om * fld);
     L.w = take(2 * (size_t)s.n_om * fld);
@@ -148,6 +151,27 @@ int ensure_attrs() {
     return DF_OK;
 }
 
+// Ladder kernel choice.  Default: the certified pivot-free blocked kernel on
+// the matrix cores, whose uncertified items go to the partial-pivoting kernel.
+// DF_LADDER_KERNEL=vector|mfma|gjb overrides the choice (for measurements):
+// vector = partial pivoting with vector FMAs for every item, mfma = partial
+// pivoting with MFMA trailing updates (n_nu <= 64).
+enum LadderKind { LK_GJB = 0, LK_VECTOR = 1, LK_MFMA = 2 };
+LadderKind ladder_kind(int n_nu) {
+    static int mode = -1;
+    if (mode < 0) {
+        const char *e = getenv("DF_LADDER_KERNEL");
+        mode = LK_GJB;
+        if (e && strcmp(e, "vector") == 0) mode = LK_VECTOR;
+        if (e && strcmp(e, "mfma") == 0) mode = LK_MFMA;
+    }
+    if (mode == LK_MFMA && ladder_mfma_padded_size(n_nu) == 0) return LK_VECTOR;
+    if (mode == LK_GJB && ladder_gjb_padded_size(n_nu) == 0) return LK_VECTOR;
+    return (LadderKind)mode;
+}
+
+constexpr int kQueueBlocks = 2048;
+
 // ---- individual stages for one instance ----------------------------------
 int stage_dual_gf(const df_inst_t &p, const Shape &s, const double *sigma, double *gd,
                   double *gr, hipStream_t st) {
@@ -190,8 +214,10 @@ int stage_bubble(const df_inst_t &p, const Shape &s, const double *gr, double *c
     return DF_OK;
 }
 
-int stage_gamma_prep(const df_inst_t &p, const Shape &s, double *gdm, double *pdm, hipStream_t st) {
+int stage_gamma_prep(const df_inst_t &p, const Shape &s, double *gdm, double *pdm, double *gtr,
+                     hipStream_t st) {
     GammaPrepArgs a{};
+    a.gtr = gtr;
     a.n_nu = s.n_nu;
     a.n_om = s.n_om;
     a.guu = p.gamma_uu;
@@ -202,11 +228,13 @@ int stage_gamma_prep(const df_inst_t &p, const Shape &s, double *gdm, double *pd
     return DF_OK;
 }
 
-int stage_ladder(const Shape &s, const double *gdm, const double *pdm, const double *chi,
-                 double *w, double *logdet, int8_t *status, int *count, hipStream_t st) {
+int stage_ladder(const Shape &s, const double *gdm, const double *pdm, const double *gtr,
+                 const double *chi, double *w, double *logdet, int8_t *status, int *counts,
+                 int *queue, hipStream_t st) {
     LadderArgs a{};
     a.gdm = gdm;
     a.pdm = pdm;
+    a.gtr = gtr;
     a.chi = chi;
     a.w = w;
     a.logdet = logdet;
@@ -216,8 +244,24 @@ int stage_ladder(const Shape &s, const double *gdm, const double *pdm, const dou
     a.N = s.N;
     a.item0 = 0;
     a.n_items = 2 * s.n_om * s.N;
-    a.fallback_count = count;
-    HIPCHK(launch_ladder_fp64(a, st));
+    a.fallback_count = counts;
+    HIPCHK(launch_zero_ints(counts, 2, st));
+    switch (ladder_kind(s.n_nu)) {
+        case LK_VECTOR: HIPCHK(launch_ladder_fp64(a, st)); break;
+        case LK_MFMA: HIPCHK(launch_ladder_mfma_f64(a, st)); break;
+        default: {
+            a.queue = queue;
+            a.queue_count = counts + 1;
+            HIPCHK(launch_ladder_gjb_f64(a, st));
+            LadderArgs b = a;
+            b.queue = nullptr;
+            b.queue_count = nullptr;
+            b.in_queue = queue;
+            b.in_count = counts + 1;
+            const int blocks = a.n_items < kQueueBlocks ? a.n_items : kQueueBlocks;
+            HIPCHK(launch_ladder_fp64_queue(b, blocks, st));
+        }
+    }
     return DF_OK;
 }
 
@@ -359,10 +403,12 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         const Layout &L = P.lay[i];
         double *gdm = at<double>(ws, P.base[i], L.gdm);
         double *pdm = at<double>(ws, P.base[i], L.pdm);
-        rc = stage_gamma_prep(inst[i], s, gdm, pdm, st);
+        double *gtr = at<double>(ws, P.base[i], L.gtr);
+        rc = stage_gamma_prep(inst[i], s, gdm, pdm, gtr, st);
         if (rc != DF_OK) return rc;
-        rc = stage_ladder(s, gdm, pdm, inst[i].chi, inst[i].w, inst[i].logdet, inst[i].status,
-                          nullptr, st);
+        rc = stage_ladder(s, gdm, pdm, gtr, inst[i].chi, inst[i].w, inst[i].logdet,
+                          inst[i].status, at<int>(ws, P.base[i], L.count),
+                          at<int>(ws, P.base[i], L.queue), st);
         if (rc != DF_OK) return rc;
     }
     return DF_OK;
@@ -402,6 +448,8 @@ int queue_iteration(const df_inst_t &p, const Shape &s, const Layout &L, void *w
     double *gr = at<double>(ws, base, L.gr);
     double *gdm = at<double>(ws, base, L.gdm);
     double *pdm = at<double>(ws, base, L.pdm);
+    double *gtr = at<double>(ws, base, L.gtr);
+    int *queue = at<int>(ws, base, L.queue);
     double *part = at<double>(ws, base, L.part);
     double *norm = at<double>(ws, base, L.norm);
     double *diff = at<double>(ws, base, L.diff);
@@ -413,7 +461,7 @@ int queue_iteration(const df_inst_t &p, const Shape &s, const Layout &L, void *w
     if (rc != DF_OK) return rc;
     rc = stage_bubble(p, s, gr, chi, st);
     if (rc != DF_OK) return rc;
-    rc = stage_ladder(s, gdm, pdm, chi, w, p.logdet, p.status, count, st);
+    rc = stage_ladder(s, gdm, pdm, gtr, chi, w, p.logdet, p.status, count, queue, st);
     if (rc != DF_OK) return rc;
     rc = stage_sigma(p, s, w, gr, part, st);
     if (rc != DF_OK) return rc;
@@ -444,7 +492,8 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     for (int i = 0; i < n_inst; ++i) {
         const Layout &L = P.lay[i];
         rc = stage_gamma_prep(inst[i], P.shape[i], at<double>(ws, P.base[i], L.gdm),
-                              at<double>(ws, P.base[i], L.pdm), st);
+                              at<double>(ws, P.base[i], L.pdm), at<double>(ws, P.base[i], L.gtr),
+                              st);
         if (rc != DF_OK) return rc;
     }
 
@@ -485,11 +534,6 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     while (it < opts->max_iter) {
         for (int i = 0; i < n_inst; ++i) {
             if (done[i]) continue;
-            int *count = at<int>(ws, P.base[i], P.lay[i].count);
-            if (hipMemsetAsync(count, 0, sizeof(int), st) != hipSuccess) {
-                cleanup();
-                return DF_E_HIP;
-            }
             if (graph) {
                 if (hipGraphLaunch(exec[i], st) != hipSuccess) {
                     cleanup();

@@ -240,7 +240,15 @@ __global__ __launch_bounds__(256) void k_gamma_prep(GammaPrepArgs a) {
         st(a.gdm, tot + e, gm);
         st(a.pdm, e, gd * gdt);
         st(a.pdm, tot + e, gm * gmt);
+        if (a.gtr) {
+            st(a.gtr, e, gdt);
+            st(a.gtr, tot + e, gmt);
+        }
     }
+}
+
+__global__ void k_zero_ints(int *p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // ------------------------------------------------------------------------
@@ -286,6 +294,11 @@ hipError_t launch_reduce_mix(const ReduceMixArgs &a, int blocks, hipStream_t s) 
 
 hipError_t launch_norm_final(const double *part, int n_part, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, part, n_part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ struct GammaPrepArgs {
     const double *guu, *gud;
     double *gdm;                     // [2][n_om][n_nu][n_nu]
     double *pdm;                     // [2][n_om][n_nu][n_nu]
+    double *gtr;                     // [2][n_om][n_nu][n_nu] (may be null)
 };
 
 struct LadderArgs {
@@ -65,6 +66,11 @@ struct LadderArgs {
     int n_nu, n_om, N;
     int item0, n_items;              // items are (c, m, q), q fastest
     int *fallback_count;             // may be null: atomically counts status != 0
+    const double *gtr;               // [2][n_om][n_nu][n_nu] gamma transposed (gjb kernel)
+    int *queue;                      // gjb: uncertified items are appended here
+    int *queue_count;                // gjb: queue length (zeroed before the launch)
+    const int *in_queue;             // pivoting kernel: process these items ...
+    const int *in_count;             // ... (count on the device) instead of item0 + block
 };
 
 hipError_t launch_dual_gf(const DualGfArgs &a, hipStream_t s);
@@ -78,5 +84,14 @@ hipError_t set_fft_lds_limits();
 // padded ladder size for n_nu, 0 if unsupported
 int ladder_padded_size(int n_nu);
 hipError_t launch_ladder_fp64(const LadderArgs &a, hipStream_t s);
+// MFMA blocked Gauss-Jordan variant (n_nu <= 64)
+int ladder_mfma_padded_size(int n_nu);
+hipError_t launch_ladder_mfma_f64(const LadderArgs &a, hipStream_t s);
+// certified pivot-free blocked Gauss-Jordan (n_nu <= 128)
+int ladder_gjb_padded_size(int n_nu);
+hipError_t launch_ladder_gjb_f64(const LadderArgs &a, hipStream_t s);
+// pivoting kernel over a device-side queue of items (grid-stride, fixed grid)
+hipError_t launch_ladder_fp64_queue(const LadderArgs &a, int blocks, hipStream_t s);
+hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
 
 }  // namespace df

@@ -55,7 +55,9 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
     const int lane = tid & 63;
     const int n_nu = a.n_nu, N = a.N;
 
-    const int item = a.item0 + blockIdx.x;
+    const int n_work = a.in_queue ? *a.in_count : 1;
+    for (int wi = a.in_queue ? (int)blockIdx.x : 0; wi < n_work; wi += (a.in_queue ? (int)gridDim.x : 1)) {
+    const int item = a.in_queue ? a.in_queue[wi] : a.item0 + blockIdx.x;
     const int q = item % N;
     const int cm = item / N;                 // c * n_om + m
     const int im = cm % a.n_om;
@@ -264,6 +266,8 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
         }
         st(a.w, ((size_t)cm * n_nu + n) * N + q, w);
     }
+    __syncthreads();   // LDS is reused by the next queued item
+    }
 }
 
 int ladder_padded_size(int n_nu) {
@@ -288,6 +292,24 @@ static hipError_t launch_one(const LadderArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_ladder_fp64<NP, TR, TC>), dim3(cnt), dim3(TR * TC), 0, s, b);
     }
     return hipGetLastError();
+}
+
+template <int NP, int TR, int TC>
+static hipError_t launch_queue(const LadderArgs &a, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_ladder_fp64<NP, TR, TC>), dim3(blocks), dim3(TR * TC), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ladder_fp64_queue(const LadderArgs &a, int blocks, hipStream_t s) {
+    switch (ladder_padded_size(a.n_nu)) {
+        case 16: return launch_queue<16, 8, 8>(a, blocks, s);
+        case 32: return launch_queue<32, 8, 8>(a, blocks, s);
+        case 48: return launch_queue<48, 16, 16>(a, blocks, s);
+        case 64: return launch_queue<64, 16, 16>(a, blocks, s);
+        case 96: return launch_queue<96, 32, 16>(a, blocks, s);
+        case 128: return launch_queue<128, 32, 16>(a, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_ladder_fp64(const LadderArgs &a, hipStream_t s) {
