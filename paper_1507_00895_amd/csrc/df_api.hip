@@ -228,9 +228,9 @@ int stage_gamma_prep(const df_inst_t &p, const Shape &s, double *gdm, double *pd
     return DF_OK;
 }
 
-int stage_ladder(const Shape &s, const double *gdm, const double *pdm, const double *gtr,
-                 const double *chi, double *w, double *logdet, int8_t *status, int *counts,
-                 int *queue, hipStream_t st) {
+int stage_ladder(const Shape &s, int prec, const double *gdm, const double *pdm,
+                 const double *gtr, const double *chi, double *w, double *logdet, int8_t *status,
+                 int *counts, int *queue, hipStream_t st) {
     LadderArgs a{};
     a.gdm = gdm;
     a.pdm = pdm;
@@ -246,6 +246,19 @@ int stage_ladder(const Shape &s, const double *gdm, const double *pdm, const dou
     a.n_items = 2 * s.n_om * s.N;
     a.fallback_count = counts;
     HIPCHK(launch_zero_ints(counts, 2, st));
+    if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(s.n_nu) != 0) {
+        a.queue = queue;
+        a.queue_count = counts + 1;
+        HIPCHK(launch_ladder_mixed(a, st));
+        LadderArgs b = a;
+        b.queue = nullptr;
+        b.queue_count = nullptr;
+        b.in_queue = queue;
+        b.in_count = counts + 1;
+        const int blocks = a.n_items < kQueueBlocks ? a.n_items : kQueueBlocks;
+        HIPCHK(launch_ladder_fp64_queue(b, blocks, st));
+        return DF_OK;
+    }
     switch (ladder_kind(s.n_nu)) {
         case LK_VECTOR: HIPCHK(launch_ladder_fp64(a, st)); break;
         case LK_MFMA: HIPCHK(launch_ladder_mfma_f64(a, st)); break;
@@ -387,7 +400,6 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
                     size_t ws_bytes, df_stream_t stream) {
     int rc = check_opts(opts, false);
     if (rc != DF_OK) return rc;
-    if (opts && opts->prec != DF_FP64) return DF_E_UNSUPPORTED;
     Plan P;
     rc = make_plan(inst, n_inst, &P);
     if (rc != DF_OK) return rc;
@@ -406,7 +418,8 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         double *gtr = at<double>(ws, P.base[i], L.gtr);
         rc = stage_gamma_prep(inst[i], s, gdm, pdm, gtr, st);
         if (rc != DF_OK) return rc;
-        rc = stage_ladder(s, gdm, pdm, gtr, inst[i].chi, inst[i].w, inst[i].logdet,
+        rc = stage_ladder(s, opts ? opts->prec : DF_FP64, gdm, pdm, gtr, inst[i].chi,
+                          inst[i].w, inst[i].logdet,
                           inst[i].status, at<int>(ws, P.base[i], L.count),
                           at<int>(ws, P.base[i], L.queue), st);
         if (rc != DF_OK) return rc;
@@ -461,7 +474,7 @@ int queue_iteration(const df_inst_t &p, const Shape &s, const Layout &L, void *w
     if (rc != DF_OK) return rc;
     rc = stage_bubble(p, s, gr, chi, st);
     if (rc != DF_OK) return rc;
-    rc = stage_ladder(s, gdm, pdm, gtr, chi, w, p.logdet, p.status, count, queue, st);
+    rc = stage_ladder(s, o.prec, gdm, pdm, gtr, chi, w, p.logdet, p.status, count, queue, st);
     if (rc != DF_OK) return rc;
     rc = stage_sigma(p, s, w, gr, part, st);
     if (rc != DF_OK) return rc;
@@ -474,7 +487,6 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
                double *diff_out, void *ws, size_t ws_bytes, df_stream_t stream) {
     int rc = check_opts(opts, true);
     if (rc != DF_OK) return rc;
-    if (opts->prec != DF_FP64) return DF_E_UNSUPPORTED;
     Plan P;
     rc = make_plan(inst, n_inst, &P);
     if (rc != DF_OK) return rc;

@@ -1,0 +1,261 @@
+// Batched Bethe-Salpeter ladder, mixed precision: FP32 inversion on the FP32
+// matrix cores, one FP64 residual correction.  Same outputs as the FP64 path
+// (eqs. dual_ladder, lin_alg_inv, the radius rule, Gamma^(2) of eq. sd).
+//
+// Per (channel, Om_m, q) work-group:
+//   1. D = 1 - gamma diag(chi) rounded to FP32 tiles; certificate (bound 0.99)
+//      as in the FP64 kernel, uncertified items are queued to the FP64
+//      partial-pivoting kernel;
+//   2. X ~ D^-1 by the certified blocked Gauss-Jordan sweep in FP32;
+//   3. Z0 = X gamma                               (FP32 MFMA)
+//      E  = gamma - D Z0 = gamma - Z0 + gamma (chi Z0)   (FP64 MFMA, exact Z0)
+//      Gamma_nn = (Z0)_nn + (X E)_nn              (FP64 accumulation)
+//   This is one step of iterative refinement of the solve D Z = gamma,
+//   restricted to the diagonal that the Schwinger-Dyson step needs.  The
+//   remaining error is of order (kappa eps32)^2 relative, with kappa the
+//   condition number of D after diagonal scaling, which the certificate
+//   bounds by 1 / (1 - 0.99): about 4e-11 at eps32 = 6e-8.
+//   log det D is the sum of the logs of the FP32 pivots, accumulated in FP64
+//   (relative accuracy of |det| about kappa * n * eps32); items near the
+//   instability fail the certificate and take the FP64 path, whose
+//   determinant is exact to FP64 rounding.
+#include "df_gj_core.hpp"
+
+namespace df {
+
+constexpr int MIX_CERT_ITERS = 6;
+constexpr double CERT_MAX_MIXED = 0.99;
+
+template <int NP> struct MixedShared {
+    union {
+        GjShared<float, NP> gj;          // during the FP32 sweep
+        struct {
+            cf Xs[NP][NP];               // X = D^-1 (FP32), all rows
+            cf Zs[NP][NP];               // Z0 = X gamma (FP32), all rows
+        } ref;                           // during the refinement
+    };
+};
+
+template <int NP>
+__global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a) {
+    constexpr int NT = NP / 16;
+    typedef MT<float>::v4 f4;
+    typedef MT<double>::v4 d4;
+    __shared__ MixedShared<NP> sh;
+    __shared__ cd ypart[NT][NP];
+    __shared__ cd tv[NP];
+    __shared__ int s_flag;
+
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int l = tid & 63;
+    const int lj = l & 15;
+    const int lg = l >> 4;
+    const int n_nu = a.n_nu, N = a.N;
+
+    const int item = a.item0 + blockIdx.x;
+    const int q = item % N;
+    const int cm = item / N;
+    const int im = cm % a.n_om;
+    const size_t nn = (size_t)n_nu * n_nu;
+    const double *gam = a.gdm + 2 * (size_t)cm * nn;
+    const double *pm = a.pdm + 2 * (size_t)cm * nn;
+    const double *chi = a.chi + 2 * ((size_t)im * n_nu) * N;   // chi[j] at chi + 2 (j N + q)
+
+    // ---- D in FP32 tiles (FP32 accumulator layout), t_i in FP64
+    f4 Cr[NT], Ci[NT];
+    cd tp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) {
+        const int j = 16 * tc + lj;
+        const cd xj = (j < n_nu) ? ld(chi, (size_t)j * N + q) : cd{0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + MT<float>::row(lg, r);
+            double dr = (i == j) ? 1.0 : 0.0, di = 0.0;
+            if (i < n_nu && j < n_nu) {
+                const cd x = ld(gam, (size_t)i * n_nu + j) * xj;
+                dr -= x.re;
+                di = -x.im;
+                tp[r] = fma_c(tp[r], ld(pm, (size_t)i * n_nu + j), xj);
+            }
+            Cr[tc][r] = (float)dr;
+            Ci[tc][r] = (float)di;
+        }
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            tp[r].re += __shfl_xor(tp[r].re, off, 64);
+            tp[r].im += __shfl_xor(tp[r].im, off, 64);
+        }
+    }
+    if (lj == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tv[16 * w + MT<float>::row(lg, r)] = tp[r];
+    }
+
+    const double cw = gj_certify<float, NP>(Cr, Ci, sh.gj, MIX_CERT_ITERS);
+    if (!(cw < CERT_MAX_MIXED)) {
+        if (tid == 0 && a.queue) a.queue[atomicAdd(a.queue_count, 1)] = item;
+        return;   // uniform: every thread of the work-group leaves here
+    }
+
+    gj_sweep<float, NP>(Cr, Ci, sh.gj);
+
+    if (w == 0) {
+        cd ldv;
+        const int stt = gj_logdet<NP>(sh.gj.pivv, &ldv);
+        if (l == 0) {
+            s_flag = stt;
+            const size_t o = (size_t)cm * N + q;
+            if (a.logdet) st(a.logdet, o, ldv);
+            if (a.status) a.status[o] = (int8_t)stt;
+            if (stt != 0 && a.fallback_count) atomicAdd(a.fallback_count, 1);
+        }
+    }
+    __syncthreads();   // also ends every use of sh.gj
+    const int stt = s_flag;
+
+    if (stt == 0) {
+        // ---- share X (all waves' block-rows)
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sh.ref.Xs[16 * w + MT<float>::row(lg, r)][16 * tc + lj] = cf{Cr[tc][r], Ci[tc][r]};
+        __syncthreads();
+
+        // ---- Z0 = X gamma on the FP32 matrix cores (block-row w)
+        f4 Zr[NT], Zi[NT];
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc) {
+            Zr[tc] = f4{0, 0, 0, 0};
+            Zi[tc] = f4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                const int k = 16 * kt + 4 * k4 + lg;
+                const cf xa = sh.ref.Xs[16 * w + lj][k];
+                const float nxi = -xa.im;
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) {
+                    const int j = 16 * tc + lj;
+                    const cd g = (k < n_nu && j < n_nu) ? ld(gam, (size_t)k * n_nu + j) : cd{0.0, 0.0};
+                    const float br = (float)g.re, bi = (float)g.im;
+                    Zr[tc] = MT<float>::mma(xa.re, br, Zr[tc]);
+                    Zr[tc] = MT<float>::mma(nxi, bi, Zr[tc]);
+                    Zi[tc] = MT<float>::mma(xa.re, bi, Zi[tc]);
+                    Zi[tc] = MT<float>::mma(xa.im, br, Zi[tc]);
+                }
+            }
+        }
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sh.ref.Zs[16 * w + MT<float>::row(lg, r)][16 * tc + lj] = cf{Zr[tc][r], Zi[tc][r]};
+        __syncthreads();
+
+        // ---- E = gamma - Z0 + gamma (chi Z0) on the FP64 matrix cores (block-row w)
+        d4 Er[NT], Ei[NT];
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc) {
+            const int j = 16 * tc + lj;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * w + MT<double>::row(lg, r);
+                const cd g = (i < n_nu && j < n_nu) ? ld(gam, (size_t)i * n_nu + j) : cd{0.0, 0.0};
+                const cf z = sh.ref.Zs[i][j];
+                Er[tc][r] = g.re - (double)z.re;
+                Ei[tc][r] = g.im - (double)z.im;
+            }
+        }
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                const int k = 16 * kt + 4 * k4 + lg;
+                const int ia = 16 * w + lj;
+                const cd ga = (ia < n_nu && 16 * kt + 4 * k4 + lg < n_nu)
+                                  ? ld(gam, (size_t)ia * n_nu + k) : cd{0.0, 0.0};
+                const double ngi = -ga.im;
+                const cd xk = (k < n_nu) ? ld(chi, (size_t)k * N + q) : cd{0.0, 0.0};
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) {
+                    const cf z = sh.ref.Zs[k][16 * tc + lj];
+                    const cd b = xk * cd{(double)z.re, (double)z.im};
+                    Er[tc] = MT<double>::mma(ga.re, b.re, Er[tc]);
+                    Er[tc] = MT<double>::mma(ngi, b.im, Er[tc]);
+                    Ei[tc] = MT<double>::mma(ga.re, b.im, Ei[tc]);
+                    Ei[tc] = MT<double>::mma(ga.im, b.re, Ei[tc]);
+                }
+            }
+        }
+
+        // ---- (X E)_nn: this wave's rows k of E against X[n][k]
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc) {
+            const int n = 16 * tc + lj;
+            cd acc = {0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = 16 * w + MT<double>::row(lg, r);
+                const cf x = sh.ref.Xs[n][k];
+                acc = fma_c(acc, cd{(double)x.re, (double)x.im}, cd{Er[tc][r], Ei[tc][r]});
+            }
+            acc.re += __shfl_xor(acc.re, 16, 64);
+            acc.im += __shfl_xor(acc.im, 16, 64);
+            acc.re += __shfl_xor(acc.re, 32, 64);
+            acc.im += __shfl_xor(acc.im, 32, 64);
+            if (lg == 0) ypart[w][n] = acc;
+        }
+    }
+    __syncthreads();
+    for (int n = tid; n < n_nu; n += NP * 4) {
+        const cd tt = tv[n];
+        cd wv;
+        if (stt == 0) {
+            const cf z = sh.ref.Zs[n][n];
+            cd y = {(double)z.re, (double)z.im};
+            for (int x = 0; x < NT; ++x) y = y + ypart[x][n];
+            wv = {y.re - 0.5 * tt.re, y.im - 0.5 * tt.im};
+        } else {
+            const cd gnn = ld(gam, (size_t)n * n_nu + n);
+            wv = {gnn.re + 0.5 * tt.re, gnn.im + 0.5 * tt.im};
+        }
+        st(a.w, ((size_t)cm * n_nu + n) * N + q, wv);
+    }
+}
+
+template <int NP>
+static hipError_t launch_mixed(const LadderArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_ladder_mixed<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+    return hipGetLastError();
+}
+
+int ladder_mixed_padded_size(int n_nu) {
+    if (n_nu <= 0) return 0;
+    if (n_nu <= 16) return 16;
+    if (n_nu <= 32) return 32;
+    if (n_nu <= 48) return 48;
+    if (n_nu <= 64) return 64;
+    return 0;   // the FP32 X and Z0 of larger matrices exceed the LDS budget
+}
+
+hipError_t launch_ladder_mixed(const LadderArgs &a, hipStream_t s) {
+    switch (ladder_mixed_padded_size(a.n_nu)) {
+        case 16: return launch_mixed<16>(a, s);
+        case 32: return launch_mixed<32>(a, s);
+        case 48: return launch_mixed<48>(a, s);
+        case 64: return launch_mixed<64>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace df
