@@ -1,5 +1,6 @@
 // C ABI of libdf: argument validation, workspace layout, launch sequencing,
-// the self-consistency loop and its optional hipGraph capture.
+// the self-consistency loop, its hipGraph capture and the fused
+// multi-instance ladder launches.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -15,6 +16,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMixBlocks = 512;
+constexpr int kQueueBlocks = 2048;
+constexpr int kMaxClasses = 16;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -26,8 +29,9 @@ int ilog2_exact(int x) {
 }
 
 struct Shape {
-    int D, nk, lognk, N, n_nu, n_om, NP;
+    int D, nk, lognk, N, n_nu, n_om;
     int chunk_len, n_chunks;
+    int items;                        // 2 n_om N ladder items
 };
 
 int check_inst(const df_inst_t &p, Shape *s) {
@@ -47,7 +51,7 @@ int check_inst(const df_inst_t &p, Shape *s) {
     s->N = (int)N;
     s->n_nu = p.n_nu;
     s->n_om = p.n_om;
-    s->NP = ladder_padded_size(p.n_nu);
+    s->items = 2 * p.n_om * (int)N;
     int nch = (512 + p.n_nu - 1) / p.n_nu;
     if (nch > p.n_om) nch = p.n_om;
     if (nch < 1) nch = 1;
@@ -58,7 +62,7 @@ int check_inst(const df_inst_t &p, Shape *s) {
 
 // Per-instance workspace regions (byte offsets from the instance base).
 struct Layout {
-    size_t gr, gdm, pdm, gtr, queue, part, norm, diff, count, gd, chi, w, sc, total;
+    size_t gr, gdm, pdm, gtr, part, norm, gd, chi, w, total;
 };
 
 Layout layout_of(const Shape &s) {
@@ -71,27 +75,34 @@ Layout layout_of(const Shape &s) {
         return at;
     };
     const size_t fld = (size_t)s.n_nu * s.N * cdb;
+    const size_t gam = 2 * (size_t)s.n_om * s.n_nu * s.n_nu * cdb;
     L.gr = take(fld);
-    L.gdm = take(2 * (size_t)s.n_om * s.n_nu * s.n_nu * cdb);
-    L.pdm = take(2 * (size_t)s.n_om * s.n_nu * s.n_nu * cdb);
-    L.gtr = take(2 * (size_t)s.n_om * s.n_nu * s.n_nu * cdb);
-    L.queue = take(2 * (size_t)s.n_om * s.N * sizeof(int));
+    L.gdm = take(gam);
+    L.pdm = take(gam);
+    L.gtr = take(gam);
     L.part = take((size_t)s.n_chunks * fld);
     L.norm = take((size_t)kMixBlocks * 2 * sizeof(double));
-    L.diff = take(2 * sizeof(double));
-    L.count = take(2 * sizeof(int));   // [0] ladders outside the radius, [1] queue length
     L.gd = take(fld);
     L.chi = take((size_t)s.n_om * fld);
     L.w = take(2 * (size_t)s.n_om * fld);
-    L.sc = take(fld);
     L.total = o;
     return L;
 }
+
+// Workspace regions shared by all instances of a call.
+struct Global {
+    size_t table;                     // LadderInst[n_inst] (fused launches)
+    size_t queue;                     // int[sum of items]: uncertified items
+    size_t ints;                      // int[kMaxClasses + n_inst]: queue lengths, outside counts
+    size_t diffs;                     // double[n_inst][2]: diff, non-finite flag
+    size_t total;
+};
 
 struct Plan {
     std::vector<Shape> shape;
     std::vector<Layout> lay;
     std::vector<size_t> base;
+    Global g;
     size_t total = 0;
 };
 
@@ -101,13 +112,26 @@ int make_plan(const df_inst_t *inst, int32_t n_inst, Plan *P) {
     P->lay.resize(n_inst);
     P->base.resize(n_inst);
     size_t off = 0;
+    size_t items = 0;
     for (int i = 0; i < n_inst; ++i) {
         const int rc = check_inst(inst[i], &P->shape[i]);
         if (rc != DF_OK) return rc;
         P->lay[i] = layout_of(P->shape[i]);
         P->base[i] = off;
         off = align_up(off + P->lay[i].total);
+        items += (size_t)P->shape[i].items;
     }
+    if (items > (size_t)0x7fffffff) return DF_E_UNSUPPORTED;
+    Global &g = P->g;
+    g.table = off;
+    off = align_up(off + (size_t)n_inst * sizeof(LadderInst));
+    g.queue = off;
+    off = align_up(off + items * sizeof(int));
+    g.ints = off;
+    off = align_up(off + (size_t)(kMaxClasses + n_inst) * sizeof(int));
+    g.diffs = off;
+    off = align_up(off + (size_t)n_inst * 2 * sizeof(double));
+    g.total = off;
     P->total = off;
     return DF_OK;
 }
@@ -119,8 +143,8 @@ int check_ws(const Plan &P, void *ws, size_t ws_bytes) {
     return DF_OK;
 }
 
-template <typename T> T *at(void *ws, size_t base, size_t off) {
-    return reinterpret_cast<T *>(static_cast<char *>(ws) + base + off);
+template <typename T> T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
 Grid grid_of(const Shape &s) {
@@ -151,13 +175,15 @@ int ensure_attrs() {
     return DF_OK;
 }
 
-// Ladder kernel choice.  Default: the certified pivot-free blocked kernel on
-// the matrix cores, whose uncertified items go to the partial-pivoting kernel.
-// DF_LADDER_KERNEL=vector|mfma|gjb overrides the choice (for measurements):
-// vector = partial pivoting with vector FMAs for every item, mfma = partial
-// pivoting with MFMA trailing updates (n_nu <= 64).
-enum LadderKind { LK_GJB = 0, LK_VECTOR = 1, LK_MFMA = 2 };
-LadderKind ladder_kind(int n_nu) {
+// ---- ladder kernel choice ---------------------------------------------------
+// Default: the certified pivot-free blocked kernel on the matrix cores (FP64,
+// or FP32 + FP64 refinement), whose uncertified items go to the
+// partial-pivoting kernel.  DF_LADDER_KERNEL=vector|mfma|gjb overrides the
+// FP64 choice for measurements: vector = partial pivoting with vector FMAs,
+// mfma = partial pivoting with MFMA trailing updates (n_nu <= 64).
+enum LadderKind { LK_GJB = 0, LK_VECTOR = 1, LK_MFMA = 2, LK_MIXED = 3 };
+
+int env_kind() {
     static int mode = -1;
     if (mode < 0) {
         const char *e = getenv("DF_LADDER_KERNEL");
@@ -165,14 +191,53 @@ LadderKind ladder_kind(int n_nu) {
         if (e && strcmp(e, "vector") == 0) mode = LK_VECTOR;
         if (e && strcmp(e, "mfma") == 0) mode = LK_MFMA;
     }
-    if (mode == LK_MFMA && ladder_mfma_padded_size(n_nu) == 0) return LK_VECTOR;
-    if (mode == LK_GJB && ladder_gjb_padded_size(n_nu) == 0) return LK_VECTOR;
-    return (LadderKind)mode;
+    return mode;
 }
 
-constexpr int kQueueBlocks = 2048;
+LadderKind ladder_kind(int n_nu, int prec) {
+    if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(n_nu) != 0) return LK_MIXED;
+    const int mode = env_kind();
+    if (mode == LK_MFMA && ladder_mfma_padded_size(n_nu) != 0) return LK_MFMA;
+    if (mode == LK_GJB && ladder_gjb_padded_size(n_nu) != 0) return LK_GJB;
+    return LK_VECTOR;
+}
 
-// ---- individual stages for one instance ----------------------------------
+// Instances that share a kernel and its padded size are fused in one launch.
+int ladder_class(int n_nu, int prec) {
+    const LadderKind k = ladder_kind(n_nu, prec);
+    int np;
+    switch (k) {
+        case LK_MIXED: np = ladder_mixed_padded_size(n_nu); break;
+        case LK_MFMA: np = ladder_mfma_padded_size(n_nu); break;
+        case LK_GJB: np = ladder_gjb_padded_size(n_nu); break;
+        default: np = ladder_padded_size(n_nu); break;
+    }
+    return (int)k * 256 + np;
+}
+
+// Launch the ladder for the items in a (single instance, or a fused table);
+// the certified kernels queue their uncertified items to the pivoting kernel.
+int launch_ladder_kind(LadderKind kind, LadderArgs a, int *queue, int *qcount, hipStream_t st) {
+    switch (kind) {
+        case LK_VECTOR: HIPCHK(launch_ladder_fp64(a, st)); return DF_OK;
+        case LK_MFMA: HIPCHK(launch_ladder_mfma_f64(a, st)); return DF_OK;
+        default: break;
+    }
+    a.queue = queue;
+    a.queue_count = qcount;
+    if (kind == LK_MIXED) HIPCHK(launch_ladder_mixed(a, st));
+    else HIPCHK(launch_ladder_gjb_f64(a, st));
+    LadderArgs b = a;
+    b.queue = nullptr;
+    b.queue_count = nullptr;
+    b.in_queue = queue;
+    b.in_count = qcount;
+    const int blocks = a.n_items < kQueueBlocks ? a.n_items : kQueueBlocks;
+    HIPCHK(launch_ladder_fp64_queue(b, blocks, st));
+    return DF_OK;
+}
+
+// ---- per-instance stages -----------------------------------------------------
 int stage_dual_gf(const df_inst_t &p, const Shape &s, const double *sigma, double *gd,
                   double *gr, hipStream_t st) {
     DualGfArgs a{};
@@ -182,7 +247,6 @@ int stage_dual_gf(const df_inst_t &p, const Shape &s, const double *sigma, doubl
     a.delta = p.delta;
     a.eps = p.eps;
     a.sigma = sigma;
-    a.gd_in = nullptr;
     a.gd_out = gd;
     a.gr_out = gr;
     a.from_gd = 0;
@@ -214,67 +278,17 @@ int stage_bubble(const df_inst_t &p, const Shape &s, const double *gr, double *c
     return DF_OK;
 }
 
-int stage_gamma_prep(const df_inst_t &p, const Shape &s, double *gdm, double *pdm, double *gtr,
+int stage_gamma_prep(const df_inst_t &p, const Shape &s, void *ws, size_t base, const Layout &L,
                      hipStream_t st) {
     GammaPrepArgs a{};
-    a.gtr = gtr;
     a.n_nu = s.n_nu;
     a.n_om = s.n_om;
     a.guu = p.gamma_uu;
     a.gud = p.gamma_ud;
-    a.gdm = gdm;
-    a.pdm = pdm;
+    a.gdm = at<double>(ws, base + L.gdm);
+    a.pdm = at<double>(ws, base + L.pdm);
+    a.gtr = at<double>(ws, base + L.gtr);
     HIPCHK(launch_gamma_prep(a, st));
-    return DF_OK;
-}
-
-int stage_ladder(const Shape &s, int prec, const double *gdm, const double *pdm,
-                 const double *gtr, const double *chi, double *w, double *logdet, int8_t *status,
-                 int *counts, int *queue, hipStream_t st) {
-    LadderArgs a{};
-    a.gdm = gdm;
-    a.pdm = pdm;
-    a.gtr = gtr;
-    a.chi = chi;
-    a.w = w;
-    a.logdet = logdet;
-    a.status = status;
-    a.n_nu = s.n_nu;
-    a.n_om = s.n_om;
-    a.N = s.N;
-    a.item0 = 0;
-    a.n_items = 2 * s.n_om * s.N;
-    a.fallback_count = counts;
-    HIPCHK(launch_zero_ints(counts, 2, st));
-    if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(s.n_nu) != 0) {
-        a.queue = queue;
-        a.queue_count = counts + 1;
-        HIPCHK(launch_ladder_mixed(a, st));
-        LadderArgs b = a;
-        b.queue = nullptr;
-        b.queue_count = nullptr;
-        b.in_queue = queue;
-        b.in_count = counts + 1;
-        const int blocks = a.n_items < kQueueBlocks ? a.n_items : kQueueBlocks;
-        HIPCHK(launch_ladder_fp64_queue(b, blocks, st));
-        return DF_OK;
-    }
-    switch (ladder_kind(s.n_nu)) {
-        case LK_VECTOR: HIPCHK(launch_ladder_fp64(a, st)); break;
-        case LK_MFMA: HIPCHK(launch_ladder_mfma_f64(a, st)); break;
-        default: {
-            a.queue = queue;
-            a.queue_count = counts + 1;
-            HIPCHK(launch_ladder_gjb_f64(a, st));
-            LadderArgs b = a;
-            b.queue = nullptr;
-            b.queue_count = nullptr;
-            b.in_queue = queue;
-            b.in_count = counts + 1;
-            const int blocks = a.n_items < kQueueBlocks ? a.n_items : kQueueBlocks;
-            HIPCHK(launch_ladder_fp64_queue(b, blocks, st));
-        }
-    }
     return DF_OK;
 }
 
@@ -323,6 +337,121 @@ int check_opts(const df_opts_t *o, bool need_loop) {
     return DF_OK;
 }
 
+// ---- the fused multi-instance iteration --------------------------------------
+struct FusedClass {
+    LadderKind kind;
+    int n_nu;                         // any member's n_nu (same padded size)
+    int t0, t1;                       // table range
+    int items;                        // total items of the class
+    size_t queue_off;                 // first queue slot (ints)
+};
+
+struct Fused {
+    std::vector<int> active;          // instance indices, in table order
+    std::vector<FusedClass> cls;
+    std::vector<LadderInst> table;    // host copy of the device table
+};
+
+// Group the active instances by ladder class and write the device table.
+// Ordinary (not captured) stream work, synchronised before returning.
+int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &act, int prec,
+                void *ws, Fused *F, hipStream_t st) {
+    F->active.clear();
+    F->cls.clear();
+    F->table.clear();
+    std::vector<int> keys;
+    for (int i : act) {
+        const int key = ladder_class(P.shape[i].n_nu, prec);
+        bool seen = false;
+        for (int k : keys) seen = seen || (k == key);
+        if (!seen) keys.push_back(key);
+    }
+    if ((int)keys.size() > kMaxClasses) return DF_E_UNSUPPORTED;
+    size_t qoff = 0;
+    for (int key : keys) {
+        FusedClass c{};
+        c.t0 = (int)F->table.size();
+        c.items = 0;
+        c.queue_off = qoff;
+        for (int i : act) {
+            if (ladder_class(P.shape[i].n_nu, prec) != key) continue;
+            const Shape &s = P.shape[i];
+            const Layout &L = P.lay[i];
+            const size_t b = P.base[i];
+            LadderInst d{};
+            d.gdm = at<double>(ws, b + L.gdm);
+            d.pdm = at<double>(ws, b + L.pdm);
+            d.gtr = at<double>(ws, b + L.gtr);
+            d.chi = inst[i].chi ? inst[i].chi : at<double>(ws, b + L.chi);
+            d.w = inst[i].w ? inst[i].w : at<double>(ws, b + L.w);
+            d.logdet = inst[i].logdet;
+            d.status = inst[i].status;
+            d.count = at<int>(ws, P.g.ints) + kMaxClasses + i;
+            d.n_nu = s.n_nu;
+            d.n_om = s.n_om;
+            d.N = s.N;
+            d.item0 = c.items;
+            c.items += s.items;
+            c.n_nu = s.n_nu;
+            c.kind = ladder_kind(s.n_nu, prec);
+            F->table.push_back(d);
+            F->active.push_back(i);
+        }
+        c.t1 = (int)F->table.size();
+        qoff += (size_t)c.items;
+        F->cls.push_back(c);
+    }
+    HIPCHK(hipMemcpyAsync(at<LadderInst>(ws, P.g.table), F->table.data(),
+                          F->table.size() * sizeof(LadderInst), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return DF_OK;
+}
+
+// Queue one outer iteration of the active instances (capturable).
+int queue_fused_iteration(const df_inst_t *inst, const Plan &P, const Fused &F,
+                          const df_opts_t &o, void *ws, hipStream_t st) {
+    int rc;
+    for (int i : F.active) {
+        const Shape &s = P.shape[i];
+        const Layout &L = P.lay[i];
+        const size_t b = P.base[i];
+        double *gr = at<double>(ws, b + L.gr);
+        double *gd = inst[i].gd ? inst[i].gd : at<double>(ws, b + L.gd);
+        double *chi = inst[i].chi ? inst[i].chi : at<double>(ws, b + L.chi);
+        rc = stage_dual_gf(inst[i], s, inst[i].sigma, gd, gr, st);
+        if (rc != DF_OK) return rc;
+        rc = stage_bubble(inst[i], s, gr, chi, st);
+        if (rc != DF_OK) return rc;
+    }
+    int *ints = at<int>(ws, P.g.ints);
+    HIPCHK(launch_zero_ints(ints, kMaxClasses + (int)P.shape.size(), st));
+    for (size_t c = 0; c < F.cls.size(); ++c) {
+        const FusedClass &k = F.cls[c];
+        LadderArgs a{};
+        a.insts = at<LadderInst>(ws, P.g.table) + k.t0;
+        a.n_insts = k.t1 - k.t0;
+        a.n_nu = k.n_nu;
+        a.item0 = 0;
+        a.n_items = k.items;
+        rc = launch_ladder_kind(k.kind, a, at<int>(ws, P.g.queue) + k.queue_off, ints + c, st);
+        if (rc != DF_OK) return rc;
+    }
+    for (int i : F.active) {
+        const Shape &s = P.shape[i];
+        const Layout &L = P.lay[i];
+        const size_t b = P.base[i];
+        double *gr = at<double>(ws, b + L.gr);
+        double *part = at<double>(ws, b + L.part);
+        double *w = inst[i].w ? inst[i].w : at<double>(ws, b + L.w);
+        rc = stage_sigma(inst[i], s, w, gr, part, st);
+        if (rc != DF_OK) return rc;
+        rc = stage_reduce_mix(s, part, inst[i].sigma_calc, inst[i].sigma, o.mix,
+                              at<double>(ws, b + L.norm), at<double>(ws, P.g.diffs) + 2 * i, st);
+        if (rc != DF_OK) return rc;
+    }
+    return DF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -360,13 +489,11 @@ int df_dual_gf(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
     if (rc != DF_OK) return rc;
     rc = check_ws(P, ws, ws_bytes);
     if (rc != DF_OK) return rc;
+    for (int i = 0; i < n_inst; ++i)
+        if (!inst[i].g || !inst[i].delta || !inst[i].eps || !inst[i].gd) return DF_E_INVAL;
     rc = ensure_attrs();
     if (rc != DF_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    for (int i = 0; i < n_inst; ++i) {
-        const df_inst_t &p = inst[i];
-        if (!p.g || !p.delta || !p.eps || !p.gd) return DF_E_INVAL;
-    }
     for (int i = 0; i < n_inst; ++i) {
         rc = stage_dual_gf(inst[i], P.shape[i], inst[i].sigma, inst[i].gd, nullptr, st);
         if (rc != DF_OK) return rc;
@@ -380,14 +507,14 @@ int df_bubble(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes, 
     if (rc != DF_OK) return rc;
     rc = check_ws(P, ws, ws_bytes);
     if (rc != DF_OK) return rc;
-    rc = ensure_attrs();
-    if (rc != DF_OK) return rc;
     for (int i = 0; i < n_inst; ++i)
         if (!inst[i].gd || !inst[i].chi) return DF_E_INVAL;
+    rc = ensure_attrs();
+    if (rc != DF_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     for (int i = 0; i < n_inst; ++i) {
         const Shape &s = P.shape[i];
-        double *gr = at<double>(ws, P.base[i], P.lay[i].gr);
+        double *gr = at<double>(ws, P.base[i] + P.lay[i].gr);
         rc = stage_transform_gd(s, inst[i].gd, gr, st);
         if (rc != DF_OK) return rc;
         rc = stage_bubble(inst[i], s, gr, inst[i].chi, st);
@@ -405,23 +532,36 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
     if (rc != DF_OK) return rc;
     rc = check_ws(P, ws, ws_bytes);
     if (rc != DF_OK) return rc;
-    rc = ensure_attrs();
-    if (rc != DF_OK) return rc;
     for (int i = 0; i < n_inst; ++i)
         if (!inst[i].gamma_uu || !inst[i].gamma_ud || !inst[i].chi || !inst[i].w) return DF_E_INVAL;
+    rc = ensure_attrs();
+    if (rc != DF_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
+    const int prec = opts ? opts->prec : DF_FP64;
+    int *ints = at<int>(ws, P.g.ints);
+    // one launch per instance with plain kernel arguments (capturable)
     for (int i = 0; i < n_inst; ++i) {
         const Shape &s = P.shape[i];
         const Layout &L = P.lay[i];
-        double *gdm = at<double>(ws, P.base[i], L.gdm);
-        double *pdm = at<double>(ws, P.base[i], L.pdm);
-        double *gtr = at<double>(ws, P.base[i], L.gtr);
-        rc = stage_gamma_prep(inst[i], s, gdm, pdm, gtr, st);
+        const size_t b = P.base[i];
+        rc = stage_gamma_prep(inst[i], s, ws, b, L, st);
         if (rc != DF_OK) return rc;
-        rc = stage_ladder(s, opts ? opts->prec : DF_FP64, gdm, pdm, gtr, inst[i].chi,
-                          inst[i].w, inst[i].logdet,
-                          inst[i].status, at<int>(ws, P.base[i], L.count),
-                          at<int>(ws, P.base[i], L.queue), st);
+        HIPCHK(launch_zero_ints(ints, kMaxClasses + n_inst, st));
+        LadderArgs a{};
+        a.gdm = at<double>(ws, b + L.gdm);
+        a.pdm = at<double>(ws, b + L.pdm);
+        a.gtr = at<double>(ws, b + L.gtr);
+        a.chi = inst[i].chi;
+        a.w = inst[i].w;
+        a.logdet = inst[i].logdet;
+        a.status = inst[i].status;
+        a.fallback_count = ints + kMaxClasses + i;
+        a.n_nu = s.n_nu;
+        a.n_om = s.n_om;
+        a.N = s.N;
+        a.item0 = 0;
+        a.n_items = s.items;
+        rc = launch_ladder_kind(ladder_kind(s.n_nu, prec), a, at<int>(ws, P.g.queue), ints, st);
         if (rc != DF_OK) return rc;
     }
     return DF_OK;
@@ -433,16 +573,17 @@ int df_sigma(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes, d
     if (rc != DF_OK) return rc;
     rc = check_ws(P, ws, ws_bytes);
     if (rc != DF_OK) return rc;
-    rc = ensure_attrs();
-    if (rc != DF_OK) return rc;
     for (int i = 0; i < n_inst; ++i)
         if (!inst[i].w || !inst[i].gd || !inst[i].sigma_calc) return DF_E_INVAL;
+    rc = ensure_attrs();
+    if (rc != DF_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     for (int i = 0; i < n_inst; ++i) {
         const Shape &s = P.shape[i];
         const Layout &L = P.lay[i];
-        double *gr = at<double>(ws, P.base[i], L.gr);
-        double *part = at<double>(ws, P.base[i], L.part);
+        const size_t b = P.base[i];
+        double *gr = at<double>(ws, b + L.gr);
+        double *part = at<double>(ws, b + L.part);
         rc = stage_transform_gd(s, inst[i].gd, gr, st);
         if (rc != DF_OK) return rc;
         rc = stage_sigma(inst[i], s, inst[i].w, gr, part, st);
@@ -453,36 +594,6 @@ int df_sigma(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes, d
     return DF_OK;
 }
 
-namespace {
-
-// Queue one full iteration of instance i on stream st.
-int queue_iteration(const df_inst_t &p, const Shape &s, const Layout &L, void *ws, size_t base,
-                    const df_opts_t &o, hipStream_t st) {
-    double *gr = at<double>(ws, base, L.gr);
-    double *gdm = at<double>(ws, base, L.gdm);
-    double *pdm = at<double>(ws, base, L.pdm);
-    double *gtr = at<double>(ws, base, L.gtr);
-    int *queue = at<int>(ws, base, L.queue);
-    double *part = at<double>(ws, base, L.part);
-    double *norm = at<double>(ws, base, L.norm);
-    double *diff = at<double>(ws, base, L.diff);
-    int *count = at<int>(ws, base, L.count);
-    double *gd = p.gd ? p.gd : at<double>(ws, base, L.gd);
-    double *chi = p.chi ? p.chi : at<double>(ws, base, L.chi);
-    double *w = p.w ? p.w : at<double>(ws, base, L.w);
-    int rc = stage_dual_gf(p, s, p.sigma, gd, gr, st);
-    if (rc != DF_OK) return rc;
-    rc = stage_bubble(p, s, gr, chi, st);
-    if (rc != DF_OK) return rc;
-    rc = stage_ladder(s, o.prec, gdm, pdm, gtr, chi, w, p.logdet, p.status, count, queue, st);
-    if (rc != DF_OK) return rc;
-    rc = stage_sigma(p, s, w, gr, part, st);
-    if (rc != DF_OK) return rc;
-    return stage_reduce_mix(s, part, p.sigma_calc, p.sigma, o.mix, norm, diff, st);
-}
-
-}  // namespace
-
 int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int32_t *iters_out,
                double *diff_out, void *ws, size_t ws_bytes, df_stream_t stream) {
     int rc = check_opts(opts, true);
@@ -492,99 +603,89 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     if (rc != DF_OK) return rc;
     rc = check_ws(P, ws, ws_bytes);
     if (rc != DF_OK) return rc;
-    rc = ensure_attrs();
-    if (rc != DF_OK) return rc;
     for (int i = 0; i < n_inst; ++i) {
         const df_inst_t &p = inst[i];
         if (!p.g || !p.delta || !p.eps || !p.gamma_uu || !p.gamma_ud || !p.sigma) return DF_E_INVAL;
     }
+    rc = ensure_attrs();
+    if (rc != DF_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     const bool graph = opts->use_graph != 0 && st != nullptr;
 
     for (int i = 0; i < n_inst; ++i) {
-        const Layout &L = P.lay[i];
-        rc = stage_gamma_prep(inst[i], P.shape[i], at<double>(ws, P.base[i], L.gdm),
-                              at<double>(ws, P.base[i], L.pdm), at<double>(ws, P.base[i], L.gtr),
-                              st);
+        rc = stage_gamma_prep(inst[i], P.shape[i], ws, P.base[i], P.lay[i], st);
         if (rc != DF_OK) return rc;
     }
 
-    std::vector<hipGraphExec_t> exec(n_inst, nullptr);
+    hipGraphExec_t exec = nullptr;
     auto cleanup = [&]() {
-        for (auto &e : exec)
-            if (e) (void)hipGraphExecDestroy(e);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
     };
-    if (graph) {
-        for (int i = 0; i < n_inst; ++i) {
-            hipGraph_t g = nullptr;
-            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-                cleanup();
-                return DF_E_HIP;
-            }
-            rc = queue_iteration(inst[i], P.shape[i], P.lay[i], ws, P.base[i], *opts, st);
-            hipError_t e = hipStreamEndCapture(st, &g);
-            if (rc != DF_OK || e != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                cleanup();
-                return rc != DF_OK ? rc : DF_E_HIP;
-            }
-            e = hipGraphInstantiate(&exec[i], g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                cleanup();
-                return DF_E_HIP;
-            }
-        }
-    }
-
-    std::vector<char> done(n_inst, 0);
+    std::vector<int> act;
+    for (int i = 0; i < n_inst; ++i) act.push_back(i);
     std::vector<double> last(n_inst, INFINITY);
-    std::vector<double> host(2);
+    std::vector<double> hdiff(2 * (size_t)n_inst);
+    std::vector<int> hints(kMaxClasses + n_inst);
+    Fused F;
+    bool rebuild = true;
     int it = 0;
     int result = DF_OK;
     bool any_fallback = false;
-    while (it < opts->max_iter) {
-        for (int i = 0; i < n_inst; ++i) {
-            if (done[i]) continue;
+    while (it < opts->max_iter && !act.empty()) {
+        if (rebuild) {
+            cleanup();
+            rc = build_fused(inst, P, act, opts->prec, ws, &F, st);
+            if (rc != DF_OK) return rc;
             if (graph) {
-                if (hipGraphLaunch(exec[i], st) != hipSuccess) {
-                    cleanup();
+                hipGraph_t g = nullptr;
+                if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
                     return DF_E_HIP;
+                rc = queue_fused_iteration(inst, P, F, *opts, ws, st);
+                const hipError_t e = hipStreamEndCapture(st, &g);
+                if (rc != DF_OK || e != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc != DF_OK ? rc : DF_E_HIP;
                 }
-            } else {
-                rc = queue_iteration(inst[i], P.shape[i], P.lay[i], ws, P.base[i], *opts, st);
-                if (rc != DF_OK) {
-                    cleanup();
-                    return rc;
-                }
+                const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e2 != hipSuccess) return DF_E_HIP;
             }
+            rebuild = false;
         }
-        ++it;
-        bool all_done = true;
-        any_fallback = false;
-        for (int i = 0; i < n_inst; ++i) {
-            if (done[i]) continue;
-            double h[2];
-            int cnt = 0;
-            if (hipMemcpyAsync(h, at<double>(ws, P.base[i], P.lay[i].diff), 2 * sizeof(double),
-                               hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipMemcpyAsync(&cnt, at<int>(ws, P.base[i], P.lay[i].count), sizeof(int),
-                               hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess) {
+        if (graph) {
+            if (hipGraphLaunch(exec, st) != hipSuccess) {
                 cleanup();
                 return DF_E_HIP;
             }
-            last[i] = h[0];
-            if (cnt) any_fallback = true;
-            if (h[1] != 0.0 || !isfinite(h[0])) {
+        } else {
+            rc = queue_fused_iteration(inst, P, F, *opts, ws, st);
+            if (rc != DF_OK) return rc;
+        }
+        ++it;
+        if (hipMemcpyAsync(hdiff.data(), at<double>(ws, P.g.diffs), hdiff.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hints.data(), at<int>(ws, P.g.ints), hints.size() * sizeof(int),
+                           hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            cleanup();
+            return DF_E_HIP;
+        }
+        any_fallback = false;
+        std::vector<int> next;
+        for (int i : act) {
+            last[i] = hdiff[2 * i];
+            if (hints[kMaxClasses + i]) any_fallback = true;
+            if (hdiff[2 * i + 1] != 0.0 || !isfinite(hdiff[2 * i])) {
                 result = DF_E_NONFINITE;
-                done[i] = 1;
                 continue;
             }
-            if (opts->tol > 0.0 && h[0] < opts->tol) done[i] = 1;
-            else all_done = false;
+            if (opts->tol > 0.0 && hdiff[2 * i] < opts->tol) continue;
+            next.push_back(i);
         }
-        if (result == DF_E_NONFINITE || all_done) break;
+        if (result == DF_E_NONFINITE) break;
+        if (next.size() != act.size()) rebuild = true;
+        act.swap(next);
     }
     cleanup();
     if (iters_out) *iters_out = it;

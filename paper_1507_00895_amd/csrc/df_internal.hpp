@@ -56,6 +56,16 @@ struct GammaPrepArgs {
     double *gtr;                     // [2][n_om][n_nu][n_nu] (may be null)
 };
 
+// One instance of a fused multi-instance ladder launch (device-side table).
+struct LadderInst {
+    const double *gdm, *pdm, *gtr, *chi;
+    double *w, *logdet;
+    int8_t *status;
+    int *count;                      // ladders outside the radius (atomic)
+    int n_nu, n_om, N;
+    int item0;                       // first global item of this instance
+};
+
 struct LadderArgs {
     const double *gdm;               // [2][n_om][n_nu][n_nu]
     const double *pdm;               // [2][n_om][n_nu][n_nu]
@@ -71,7 +81,30 @@ struct LadderArgs {
     int *queue_count;                // gjb: queue length (zeroed before the launch)
     const int *in_queue;             // pivoting kernel: process these items ...
     const int *in_count;             // ... (count on the device) instead of item0 + block
+    const LadderInst *insts;         // non-null: fused launch over n_insts instances,
+    int n_insts;                     // items are global; the fields above are resolved per item
 };
+
+// Fused launches: find the instance of a global item, fill the per-instance
+// fields of a, return the item's index within its instance.
+__device__ __forceinline__ int resolve_item(LadderArgs &a, int item) {
+    if (!a.insts) return item;
+    int k = 0;
+    while (k + 1 < a.n_insts && a.insts[k + 1].item0 <= item) ++k;
+    const LadderInst &d = a.insts[k];
+    a.gdm = d.gdm;
+    a.pdm = d.pdm;
+    a.gtr = d.gtr;
+    a.chi = d.chi;
+    a.w = d.w;
+    a.logdet = d.logdet;
+    a.status = d.status;
+    a.fallback_count = d.count;
+    a.n_nu = d.n_nu;
+    a.n_om = d.n_om;
+    a.N = d.N;
+    return item - d.item0;
+}
 
 hipError_t launch_dual_gf(const DualGfArgs &a, hipStream_t s);
 hipError_t launch_bubble(const BubbleArgs &a, hipStream_t s);

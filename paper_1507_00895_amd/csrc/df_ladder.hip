@@ -33,7 +33,7 @@ __device__ __forceinline__ unsigned pivot_key(double mag, int row) {
 }
 
 template <int NP, int TR, int TC>
-__global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
+__global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a0) {
     constexpr int NT = TR * TC;
     constexpr int BR = NP / TR;
     constexpr int BC = NP / TC;
@@ -53,11 +53,12 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a) {
     const int tid = threadIdx.x;
     const int tr = tid / TC, tc = tid % TC;
     const int lane = tid & 63;
+    const int n_work = a0.in_queue ? *a0.in_count : 1;
+    for (int wi = a0.in_queue ? (int)blockIdx.x : 0; wi < n_work;
+         wi += (a0.in_queue ? (int)gridDim.x : 1)) {
+    LadderArgs a = a0;
+    const int item = resolve_item(a, a0.in_queue ? a0.in_queue[wi] : a0.item0 + blockIdx.x);
     const int n_nu = a.n_nu, N = a.N;
-
-    const int n_work = a.in_queue ? *a.in_count : 1;
-    for (int wi = a.in_queue ? (int)blockIdx.x : 0; wi < n_work; wi += (a.in_queue ? (int)gridDim.x : 1)) {
-    const int item = a.in_queue ? a.in_queue[wi] : a.item0 + blockIdx.x;
     const int q = item % N;
     const int cm = item / N;                 // c * n_om + m
     const int im = cm % a.n_om;

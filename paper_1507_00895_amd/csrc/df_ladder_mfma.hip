@@ -49,7 +49,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <int NP>
-__global__ __launch_bounds__(NP * 4) void k_ladder_mfma_f64(LadderArgs a) {
+__global__ __launch_bounds__(NP * 4) void k_ladder_mfma_f64(LadderArgs a0) {
     constexpr int NT = NP / 16;      // tiles per row / column, = waves
     static_assert(NP % 16 == 0 && NP <= 64, "one panel row per lane");
 
@@ -68,9 +68,10 @@ __global__ __launch_bounds__(NP * 4) void k_ladder_mfma_f64(LadderArgs a) {
     const int l = tid & 63;
     const int lj = l & 15;           // column inside a tile
     const int lg = l >> 4;           // row group: rows lg + 4 r, r = 0..3
+    LadderArgs a = a0;
+    const int gitem = a0.item0 + blockIdx.x;            // global item (fused launches)
+    const int item = resolve_item(a, gitem);
     const int n_nu = a.n_nu, N = a.N;
-
-    const int item = a.item0 + blockIdx.x;
     const int q = item % N;
     const int cm = item / N;
     const int im = cm % a.n_om;

@@ -37,7 +37,7 @@ template <int NP> struct MixedShared {
 };
 
 template <int NP>
-__global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a) {
+__global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a0) {
     constexpr int NT = NP / 16;
     typedef MT<float>::v4 f4;
     typedef MT<double>::v4 d4;
@@ -51,9 +51,10 @@ __global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a) {
     const int l = tid & 63;
     const int lj = l & 15;
     const int lg = l >> 4;
+    LadderArgs a = a0;
+    const int gitem = a0.item0 + blockIdx.x;            // global item (fused launches)
+    const int item = resolve_item(a, gitem);
     const int n_nu = a.n_nu, N = a.N;
-
-    const int item = a.item0 + blockIdx.x;
     const int q = item % N;
     const int cm = item / N;
     const int im = cm % a.n_om;
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a) {
 
     const double cw = gj_certify<float, NP>(Cr, Ci, sh.gj, MIX_CERT_ITERS);
     if (!(cw < CERT_MAX_MIXED)) {
-        if (tid == 0 && a.queue) a.queue[atomicAdd(a.queue_count, 1)] = item;
+        if (tid == 0 && a.queue) a.queue[atomicAdd(a.queue_count, 1)] = gitem;
         return;   // uniform: every thread of the work-group leaves here
     }
 

@@ -237,3 +237,57 @@ def test_full_workload_one_iteration_sampled(torch_dev, name):
         sc = host(x.sigma_calc)
         assert rel(sc, O.sigma_fft(W, gd, p.D, p.nk, p.beta)) <= TOL64
         assert rel(host(x.sigma), 0.5 * sc) <= 1e-15
+
+
+UNEVEN = [
+    (2, 16, 32, 7, 12.0, 1.5, 0.1),
+    (3, 4, 64, 7, 20.0, 2.5, 0.1),
+    (2, 8, 16, 3, 6.0, 3.5, 0.1),
+    (3, 4, 96, 5, 9.0, 1.2, 0.1),
+    (2, 4, 128, 3, 5.0, 2.0, 0.1),
+    (2, 8, 48, 11, 24.0, 3.0, 0.1),
+    (2, 16, 32, 7, 12.0, 2.5, 0.1),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_uneven_instances_match_oracle(torch_dev, prec):
+    """Uneven instances (D, nk, n_nu, n_om all different) in fused ladder launches."""
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    probs = [I.atomic_limit_problem(*s) for s in UNEVEN]
+    insts = [B.make_instance(p) for p in probs]
+    ws = B.workspace(insts)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    B.df_iterate(insts, ws, B.make_opts(prec=prec, mix=0.5, max_iter=3, use_graph=1),
+                 stream=s.cuda_stream)
+    s.synchronize()
+    tol = TOL64 if prec == 0 else 1e-9
+    for p, x in zip(probs, insts):
+        r = O.iterate(p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta, p.n_om,
+                      alpha=0.5, max_iter=3)
+        assert rel(host(x.sigma), r.sigma) <= tol, p.summary()
+
+
+def test_fused_convergence_matches_single_instance_runs(torch_dev):
+    """Instances leave the fused graph as they converge; each ends where it would alone."""
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    probs = [I.atomic_limit_problem(*s) for s in UNEVEN[:4]]
+    insts = [B.make_instance(p) for p in probs]
+    ws = B.workspace(insts)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    code, iters, diffs = B.df_iterate(insts, ws, B.make_opts(mix=0.5, tol=1e-10, max_iter=200,
+                                                              use_graph=1), stream=s.cuda_stream)
+    s.synchronize()
+    assert code == B.DF_OK and all(d < 1e-10 for d in diffs)
+    for p, x in zip(probs, insts):
+        one = B.make_instance(p)
+        ws1 = B.workspace([one])
+        torch.cuda.synchronize()
+        c1, it1, d1 = B.df_iterate([one], ws1, B.make_opts(mix=0.5, tol=1e-10, max_iter=200,
+                                                           use_graph=1), stream=s.cuda_stream)
+        s.synchronize()
+        assert np.array_equal(host(one.sigma), host(x.sigma))
