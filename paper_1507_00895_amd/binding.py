@@ -248,3 +248,83 @@ def df_iterate(insts, ws, opts: DfOpts, stream=None, allow=(DF_OK, DF_W_FALLBACK
                              diffs, _ptr(ws), ws.numel(), _stream(stream))
     _check("df_iterate", code, ok=allow)
     return code, int(iters.value), list(diffs)
+
+
+# ---------------------------------------------------------------------------
+# learned warm start (include/df_mlp.h)
+# ---------------------------------------------------------------------------
+MLP_EXPORTED = ("df_mlp_param_count", "df_mlp_workspace_size", "df_mlp_forward",
+                "df_mlp_loss_grad", "df_mlp_adam")
+
+
+def _mlp_lib():
+    lib = load()
+    if getattr(lib, "_mlp_ready", False):
+        return lib
+    P = ctypes.POINTER
+    lib.df_mlp_param_count.argtypes = [ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_size_t)]
+    lib.df_mlp_workspace_size.argtypes = [ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32,
+                                          P(ctypes.c_size_t)]
+    lib.df_mlp_forward.argtypes = [ctypes.c_int32, P(ctypes.c_int32), ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.c_void_p]
+    lib.df_mlp_loss_grad.argtypes = [ctypes.c_int32, P(ctypes.c_int32), ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.c_void_p]
+    lib.df_mlp_adam.argtypes = [ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p]
+    for name in MLP_EXPORTED:
+        getattr(lib, name).restype = ctypes.c_int
+    lib._mlp_ready = True
+    return lib
+
+
+def _dims(dims):
+    arr = (ctypes.c_int32 * len(dims))(*[int(x) for x in dims])
+    return len(dims) - 1, arr
+
+
+def df_mlp_param_count(dims) -> int:
+    n, arr = _dims(dims)
+    c = ctypes.c_size_t(0)
+    _check("df_mlp_param_count", _mlp_lib().df_mlp_param_count(n, arr, ctypes.byref(c)))
+    return int(c.value)
+
+
+def mlp_workspace(dims, batch, device="cuda"):
+    import torch
+    n, arr = _dims(dims)
+    c = ctypes.c_size_t(0)
+    _check("df_mlp_workspace_size", _mlp_lib().df_mlp_workspace_size(n, arr, int(batch), ctypes.byref(c)))
+    buf = torch.empty(int(c.value) + 256, dtype=torch.uint8, device=device)
+    off = (-int(buf.data_ptr())) % 256
+    return buf[off:off + int(c.value)]
+
+
+def _f32(t, name):
+    import torch
+    if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+        raise TypeError(f"{name} must be a contiguous float32 device tensor")
+    return int(t.data_ptr())
+
+
+def df_mlp_forward(dims, params, X, Y, ws, stream=None):
+    n, arr = _dims(dims)
+    return _check("df_mlp_forward", _mlp_lib().df_mlp_forward(
+        n, arr, _f32(params, "params"), _f32(X, "X"), int(X.shape[0]), _f32(Y, "Y"),
+        _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def df_mlp_loss_grad(dims, params, X, T, grads, loss, ws, stream=None):
+    n, arr = _dims(dims)
+    return _check("df_mlp_loss_grad", _mlp_lib().df_mlp_loss_grad(
+        n, arr, _f32(params, "params"), _f32(X, "X"), _f32(T, "T"), int(X.shape[0]),
+        _f32(grads, "grads"), None if loss is None else _f32(loss, "loss"), _ptr(ws), ws.numel(),
+        _stream(stream)))
+
+
+def df_mlp_adam(params, grads, m, v, step, lr, stream=None):
+    return _check("df_mlp_adam", _mlp_lib().df_mlp_adam(
+        params.numel(), _f32(params, "params"), _f32(grads, "grads"), _f32(m, "m"), _f32(v, "v"),
+        int(step), float(lr), _stream(stream)))

@@ -1,0 +1,260 @@
+"""Learned warm start of the dual self-energy.
+
+A small MLP maps per-(instance, k) features to Sigma~(k, nu) at the positive
+fermionic frequencies; Sigma~ at negative frequencies follows by conjugation
+(Sigma~(-nu) = Sigma~(nu)*).  The prediction only replaces the zero start of
+df_iterate, which still runs to the same tolerance: results stay those of the
+method, only the iteration count changes.
+
+Every numeric step runs in libdf's HIP kernels: the training data come from
+df_iterate, the coarse dual-propagator features from df_dual_gf, training and
+inference from df_mlp_loss_grad / df_mlp_adam / df_mlp_forward.  torch holds
+device buffers and does index bookkeeping (minibatch gathers, reshapes).
+
+Features (one row per k point of an instance; 2D square lattices):
+  * instance: U, beta, t, D (standardised over the training set);
+  * k: five point-group-invariant combinations of cos k_i and cos 2k_i;
+  * coarse dual propagator: G~0 of the instance on an 8 x 8 grid at the four
+    lowest positive Matsubara frequencies, at the 15 points of the irreducible
+    wedge 0 <= k_y <= k_x <= pi (real and imaginary parts: 120 numbers).
+Targets: Re and Im of the converged Sigma~(k, nu_n), n = 0 .. n_nu/2 - 1,
+standardised per output.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import binding as B
+from . import inputs as I
+
+HIDDEN = (256, 256, 256)
+
+
+@dataclasses.dataclass
+class WarmStartConfig:
+    nk: int = 16
+    n_nu: int = 32
+    n_om: int = 7
+    t: float = 0.1
+    U_range: tuple = (1.0, 4.0)
+    beta_range: tuple = (5.0, 20.0)
+    tol: float = 1e-8
+    mix: float = 0.5
+
+    def problem(self, U: float, beta: float):
+        return I.atomic_limit_problem(2, self.nk, self.n_nu, self.n_om, beta, U, self.t)
+
+
+def draw(n: int, seed: int, cfg: WarmStartConfig):
+    rng = np.random.default_rng(seed)
+    return [(float(rng.uniform(*cfg.U_range)), float(rng.uniform(*cfg.beta_range))) for _ in range(n)]
+
+
+# ---------------------------------------------------------------- features
+WEDGE = [(x, y) for x in range(5) for y in range(x + 1)]          # 15 points of the 8x8 wedge
+
+
+def k_features(nk: int) -> np.ndarray:
+    """Point-group-invariant functions of k on the nk x nk grid, [N, 5]."""
+    k = I.kpoints(2, nk)
+    c1, c2 = np.cos(k[:, 0]), np.cos(k[:, 1])
+    d1, d2 = np.cos(2 * k[:, 0]), np.cos(2 * k[:, 1])
+    return np.stack([(c1 + c2) / 2, c1 * c2, (d1 + d2) / 2, d1 * d2, (c1 * d2 + d1 * c2) / 2], axis=1)
+
+
+def coarse_gd0(params: List[tuple], cfg: WarmStartConfig, device="cuda") -> np.ndarray:
+    """G~0 on the 8x8 grid at the 4 lowest positive nu, wedge points: [n, 120] (df_dual_gf)."""
+    import torch
+    insts = []
+    for U, beta in params:
+        g = I.atom_g(8, beta, U)
+        c = dict(dtype=torch.complex128, device=device)
+        insts.append(B.Instance(
+            D=2, nk=8, n_nu=8, n_om=1, beta=beta,
+            g=torch.as_tensor(g, **c), delta=torch.as_tensor(I.atom_delta(g, 2, cfg.t), **c),
+            eps=torch.as_tensor(I.dispersion_hypercubic(2, 8, cfg.t), dtype=torch.float64, device=device),
+            gamma_uu=None, gamma_ud=None, gd=torch.zeros((8, 64), **c)))
+    ws = B.workspace(insts, device=device)
+    B.df_dual_gf(insts, ws)
+    torch.cuda.synchronize()
+    idx = [x * 8 + y for x, y in WEDGE]
+    out = []
+    for x in insts:
+        gd = x.gd[4:8][:, idx].cpu().numpy()                        # nu_0 .. nu_3
+        out.append(np.concatenate([gd.real.ravel(), gd.imag.ravel()]))
+    return np.array(out)
+
+
+def build_features(params: List[tuple], cfg: WarmStartConfig, device="cuda") -> np.ndarray:
+    """[n * N, 129] feature rows, instance-major."""
+    N = cfg.nk ** 2
+    kf = k_features(cfg.nk)
+    g0 = coarse_gd0(params, cfg, device)
+    rows = []
+    for (U, beta), gsum in zip(params, g0):
+        inst = np.array([U, beta, cfg.t, 2.0])
+        rows.append(np.concatenate([np.tile(inst, (N, 1)), kf, np.tile(gsum, (N, 1))], axis=1))
+    return np.concatenate(rows, axis=0)
+
+
+# ---------------------------------------------------------------- data from the method
+def converge(params: List[tuple], cfg: WarmStartConfig, sigma0: Optional[list] = None,
+             batch: int = 64, device="cuda"):
+    """Run df_iterate to cfg.tol for every instance (fused batches).
+
+    Returns (sigma list [n_nu x N] numpy, iteration counts, seconds per batch).
+    """
+    import torch
+    sig, its, secs = [], [], []
+    stream = torch.cuda.Stream(device=device)
+    for s in range(0, len(params), batch):
+        chunk = params[s:s + batch]
+        insts = [B.make_instance(cfg.problem(U, beta), device=device, outputs=False)
+                 for U, beta in chunk]
+        if sigma0 is not None:
+            for x, s0 in zip(insts, sigma0[s:s + batch]):
+                x.sigma.copy_(torch.as_tensor(s0))
+        ws = B.workspace(insts, device=device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, it, diffs = B.df_iterate(insts, ws, B.make_opts(mix=cfg.mix, tol=cfg.tol, max_iter=500,
+                                                              use_graph=1),
+                                       stream=stream.cuda_stream,
+                                       allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
+        stream.synchronize()
+        secs.append(time.perf_counter() - t0)
+        its.append(it)
+        sig.extend(x.sigma.cpu().numpy() for x in insts)
+    return sig, its, secs
+
+
+def targets_from_sigma(sigmas, cfg: WarmStartConfig) -> np.ndarray:
+    """[n * N, n_nu] rows: Re and Im of Sigma~ at the positive frequencies."""
+    h = cfg.n_nu // 2
+    rows = []
+    for s in sigmas:
+        pos = s[h:].T                                              # [N, h], nu_0 .. nu_{h-1}
+        rows.append(np.concatenate([pos.real, pos.imag], axis=1))
+    return np.concatenate(rows, axis=0)
+
+
+def sigma_from_rows(rows: np.ndarray, cfg: WarmStartConfig) -> np.ndarray:
+    """Inverse of targets_from_sigma for one instance, with Sigma~(-nu) = Sigma~(nu)*."""
+    h = cfg.n_nu // 2
+    pos = (rows[:, :h] + 1j * rows[:, h:]).T                        # [h, N]
+    return np.concatenate([np.conj(pos[::-1]), pos], axis=0)
+
+
+# ---------------------------------------------------------------- the network on the GPU
+def _scale(std: np.ndarray) -> np.ndarray:
+    return np.where(std > 1e-12 * max(float(np.max(std)), 1e-300), std, 1.0)
+
+
+class WarmStartNet:
+    def __init__(self, n_in: int, n_out: int, seed: int = 0, device="cuda"):
+        import torch
+        self.dims = [n_in, *HIDDEN, n_out]
+        self.device = device
+        rng = np.random.default_rng(seed)
+        flat = []
+        for l in range(len(self.dims) - 1):
+            fan_in = self.dims[l]
+            flat.append(rng.standard_normal(self.dims[l + 1] * fan_in) * math.sqrt(2.0 / fan_in))
+            flat.append(np.zeros(self.dims[l + 1]))
+        p = np.concatenate(flat).astype(np.float32)
+        assert p.size == B.df_mlp_param_count(self.dims)
+        self.params = torch.as_tensor(p, device=device)
+        self.x_mean = self.x_std = self.y_mean = self.y_std = None
+
+    def fit(self, X: np.ndarray, Y: np.ndarray, steps: int = 2000, batch: int = 4096,
+            lr: float = 2e-3, seed: int = 1, log_every: int = 0):
+        import torch
+        dev = self.device
+        # constant columns (t and D of a one-lattice training set) stay unscaled
+        self.x_mean, self.x_std = X.mean(0), _scale(X.std(0))
+        self.y_mean, self.y_std = Y.mean(0), _scale(Y.std(0))
+        Xs = torch.as_tensor(((X - self.x_mean) / self.x_std).astype(np.float32), device=dev)
+        Ys = torch.as_tensor(((Y - self.y_mean) / self.y_std).astype(np.float32), device=dev)
+        n = Xs.shape[0]
+        batch = min(batch, n)
+        grads = torch.zeros_like(self.params)
+        m = torch.zeros_like(self.params)
+        v = torch.zeros_like(self.params)
+        loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        ws = B.mlp_workspace(self.dims, batch, device=dev)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed)
+        history = []
+        for step in range(1, steps + 1):
+            idx = torch.randint(0, n, (batch,), device=dev, generator=gen)
+            xb = Xs.index_select(0, idx).contiguous()
+            yb = Ys.index_select(0, idx).contiguous()
+            B.df_mlp_loss_grad(self.dims, self.params, xb, yb, grads, loss, ws)
+            cur_lr = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps)) + 1e-5
+            B.df_mlp_adam(self.params, grads, m, v, step, cur_lr)
+            if step == 1 or step == steps or (log_every and step % log_every == 0):
+                history.append((step, float(loss.item())))
+        return history
+
+    def predict(self, X: np.ndarray) -> np.ndarray:
+        import torch
+        Xs = torch.as_tensor(((X - self.x_mean) / self.x_std).astype(np.float32), device=self.device)
+        Y = torch.empty((Xs.shape[0], self.dims[-1]), dtype=torch.float32, device=self.device)
+        ws = B.mlp_workspace(self.dims, Xs.shape[0], device=self.device)
+        B.df_mlp_forward(self.dims, self.params, Xs, Y, ws)
+        return Y.cpu().numpy().astype(np.float64) * self.y_std + self.y_mean
+
+
+def train_and_evaluate(n_train: int = 256, n_test: int = 16, steps: int = 2000,
+                       cfg: Optional[WarmStartConfig] = None, seed_train: int = 895,
+                       seed_test: int = 896, device="cuda"):
+    """Generate converged Sigma~ with the method, train, compare cold and warm starts."""
+    cfg = cfg or WarmStartConfig()
+    N = cfg.nk ** 2
+    t0 = time.perf_counter()
+    ptrain = draw(n_train, seed_train, cfg)
+    sig, its_train, _ = converge(ptrain, cfg, device=device)
+    t_data = time.perf_counter() - t0
+    X = build_features(ptrain, cfg, device)
+    Y = targets_from_sigma(sig, cfg)
+    net = WarmStartNet(X.shape[1], Y.shape[1], device=device)
+    t1 = time.perf_counter()
+    hist = net.fit(X, Y, steps=steps)
+    t_train = time.perf_counter() - t1
+
+    ptest = draw(n_test, seed_test, cfg)
+    ta = time.perf_counter()
+    Xt = build_features(ptest, cfg, device)
+    pred = net.predict(Xt)
+    t_inf = time.perf_counter() - ta
+    warm0 = [sigma_from_rows(pred[i * N:(i + 1) * N], cfg) for i in range(n_test)]
+    sig_cold, it_cold, sec_cold = converge(ptest, cfg, batch=1, device=device)
+    sig_warm, it_warm, sec_warm = converge(ptest, cfg, sigma0=warm0, batch=1, device=device)
+    rel_pred = [float(np.linalg.norm(w - c) / np.linalg.norm(c)) for w, c in zip(warm0, sig_cold)]
+    rel_fixed = [float(np.linalg.norm(w - c) / np.linalg.norm(c)) for w, c in zip(sig_warm, sig_cold)]
+    return {
+        "workload": f"2D {cfg.nk}x{cfg.nk}, n_nu {cfg.n_nu}, n_om {cfg.n_om}, t {cfg.t}, "
+                    f"U in {cfg.U_range}, beta in {cfg.beta_range}, tol {cfg.tol}",
+        "n_train": n_train, "n_test": n_test, "train_steps": steps,
+        "train_loss_first_last": [hist[0][1], hist[-1][1]],
+        "seconds_data": t_data, "seconds_train": t_train, "seconds_inference": t_inf,
+        "iterations_cold": it_cold, "iterations_warm": it_warm,
+        "mean_iterations_cold": float(np.mean(it_cold)), "mean_iterations_warm": float(np.mean(it_warm)),
+        "mean_seconds_cold": float(np.mean(sec_cold)),
+        "mean_seconds_warm": float(np.mean(sec_warm)) + t_inf / n_test,
+        "prediction_rel_error_mean": float(np.mean(rel_pred)),
+        "fixed_point_rel_diff_max": float(np.max(rel_fixed)),
+        "train_iterations_mean": float(np.mean(its_train)),
+    }
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+    n = int(sys.argv[1]) if len(sys.argv) > 1 else 256
+    print(json.dumps(train_and_evaluate(n_train=n)))

@@ -12,18 +12,27 @@ import pytest
 from paper_1507_00895_amd import binding as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "df.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("df.h", "df_mlp.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(df_\w+)\s*\(", text, re.M)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(df_\w+)\s*\(", text, re.M))
+    return sorted(names)
+
+
+def test_every_header_is_checked():
+    present = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                     if f.endswith(".h"))
+    assert present == sorted(HEADERS)
 
 
 def test_library_exports_every_declared_symbol():
     lib = B.load()
     decl = declared_functions()
-    assert set(decl) == set(B.EXPORTED)
+    assert set(decl) == set(B.EXPORTED) | set(B.MLP_EXPORTED)
     for name in decl:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
@@ -105,3 +114,26 @@ def test_workspace_grows_with_instances():
     assert lib.df_workspace_size(one, 1, None, ctypes.byref(a)) == 0
     assert lib.df_workspace_size(two, 2, None, ctypes.byref(b)) == 0
     assert b.value > a.value
+
+
+def test_mlp_host_validation():
+    lib = B._mlp_lib()
+    assert B.df_mlp_param_count([5, 7, 3]) == 5 * 7 + 7 + 7 * 3 + 3
+    n, dims = B._dims([5, 7, 3])
+    size = ctypes.c_size_t(0)
+    assert lib.df_mlp_workspace_size(n, dims, 0, ctypes.byref(size)) == B.DF_E_INVAL
+    assert lib.df_mlp_workspace_size(n, dims, 10, ctypes.byref(size)) == B.DF_OK
+    assert size.value > 0 and size.value % 256 == 0
+    bad = (ctypes.c_int32 * 3)(5, 0, 3)
+    assert lib.df_mlp_param_count(2, bad, ctypes.byref(size)) == B.DF_E_INVAL
+    assert lib.df_mlp_param_count(0, dims, ctypes.byref(size)) == B.DF_E_INVAL
+    assert lib.df_mlp_param_count(9, dims, ctypes.byref(size)) == B.DF_E_INVAL
+    assert lib.df_mlp_forward(n, dims, None, None, 4, None, None, 0, None) == B.DF_E_INVAL
+    fake = 0x1000
+    assert lib.df_mlp_forward(n, dims, fake, fake, 4, fake, None, 0, None) == B.DF_E_WORKSPACE
+    assert lib.df_mlp_forward(n, dims, fake, fake, 4, fake, fake + 8, 1 << 30, None) == B.DF_E_WORKSPACE
+    assert lib.df_mlp_loss_grad(n, dims, fake, fake, None, 4, fake, None, fake, 1 << 30,
+                                None) == B.DF_E_INVAL
+    assert lib.df_mlp_adam(0, fake, fake, fake, fake, 1, 1e-3, None) == B.DF_E_INVAL
+    assert lib.df_mlp_adam(10, fake, fake, fake, fake, 0, 1e-3, None) == B.DF_E_INVAL
+    assert lib.df_mlp_adam(10, fake, fake, fake, fake, 1, 0.0, None) == B.DF_E_INVAL

@@ -328,3 +328,59 @@ def test_regression_markers_from_golden():
     r = O.iterate(p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta, p.n_om,
                   alpha=0.5, max_iter=10)
     assert np.allclose(r.history, s["diff_history_10"], rtol=1e-10)
+
+
+# ---------------------------------------------------------------- warm-start network reference
+def test_mlp_reference_gradient_matches_finite_differences():
+    from oracle import mlp_ref as R
+    rng = np.random.default_rng(11)
+    dims = [5, 7, 6, 3]
+    n_par = sum(dims[l + 1] * dims[l] + dims[l + 1] for l in range(3))
+    p = 0.4 * rng.standard_normal(n_par)
+    X = rng.standard_normal((9, 5))
+    T = rng.standard_normal((9, 3))
+    loss, g = R.loss_grad(p, dims, X, T)
+    h = 1e-6
+    for i in rng.choice(n_par, 25, replace=False):
+        e = np.zeros(n_par)
+        e[i] = h
+        fd = (R.loss_grad(p + e, dims, X, T)[0] - R.loss_grad(p - e, dims, X, T)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(fd))
+    # a single linear layer reduces to least squares: gradient closed form
+    W = rng.standard_normal((2, 4))
+    b = rng.standard_normal(2)
+    X1 = rng.standard_normal((6, 4))
+    T1 = rng.standard_normal((6, 2))
+    _, g1 = R.loss_grad(np.concatenate([W.ravel(), b]), [4, 2], X1, T1)
+    r = X1 @ W.T + b - T1
+    assert np.allclose(g1[:8].reshape(2, 4), 2 * r.T @ X1 / r.size)
+    assert np.allclose(g1[8:], 2 * r.sum(0) / r.size)
+
+
+# ---------------------------------------------------------------- warm-start host logic
+def test_warmstart_features_are_point_group_invariant():
+    from paper_1507_00895_amd import warmstart as W
+    nk = 16
+    f = W.k_features(nk).reshape(nk, nk, -1)
+    i = np.arange(nk)
+    assert np.allclose(f, f.transpose(1, 0, 2))                    # k_x <-> k_y
+    assert np.allclose(f, f[(-i) % nk])                            # k_x -> -k_x
+    assert np.allclose(f, f[:, (-i) % nk])                         # k_y -> -k_y
+    # the 15 wedge points of the 8x8 grid cover every C4v orbit once
+    orbits = set()
+    for x in range(8):
+        for y in range(8):
+            a, b = min(x, 8 - x), min(y, 8 - y)
+            orbits.add((max(a, b), min(a, b)))
+    assert sorted(orbits) == sorted(W.WEDGE)
+
+
+def test_warmstart_target_layout_round_trip():
+    from paper_1507_00895_amd import warmstart as W
+    cfg = W.WarmStartConfig(nk=4, n_nu=8, n_om=3)
+    rng = np.random.default_rng(2)
+    pos = rng.standard_normal((4, 16)) + 1j * rng.standard_normal((4, 16))
+    sig = np.concatenate([np.conj(pos[::-1]), pos], axis=0)          # Sigma(-nu) = Sigma(nu)*
+    rows = W.targets_from_sigma([sig], cfg)
+    assert rows.shape == (16, 8)
+    assert np.array_equal(W.sigma_from_rows(rows, cfg), sig)
