@@ -1,7 +1,7 @@
 """Benchmark of the ladder dual-fermion hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|mixed]
-                    [--no-cpu-baseline] [--no-converge]
+                    [--no-cpu-baseline] [--no-converge] [--no-warm]
 
 Workload: 2D square lattice 32x32, n_nu = 64, n_om = 31, beta = 20,
 U in {1, 2, 4} (three instances, t = 0.1), Hubbard-atom inputs.  A step is
@@ -10,8 +10,12 @@ every (Om, q), Schwinger-Dyson, mixing and the convergence measure) of all
 three instances.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line.  value = (q, Om, channel) ladder solves per second of
-whole iterations; the ladder kernel's own rate, seconds to a converged
-Sigma~ (tol 1e-8, cold start) and the CPU oracle rate are reported beside it.
+whole iterations of the --prec path; beside it: the ladder kernel's own rate
+and roofline, and under "paths" the ladder rate and seconds per converged
+Sigma~ (tol 1e-8) of the plain FP64 path, the mixed-precision path and the
+FP64 path warm-started by the learned network (trained inside the run on
+converged Sigma~ of the same shape; its cost is reported separately), and
+the CPU oracle rate.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -67,7 +71,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the seconds-per-converged-Sigma~ legs of all paths")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-started path")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default ladder kernels")
+    ap.add_argument("--warm-train", type=int, default=48,
+                    help="converged instances the warm-start network is trained on")
+    ap.add_argument("--warm-steps", type=int, default=2000)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
@@ -120,6 +130,96 @@ def cpu_baseline(problems, budget_s: float = 20.0):
                        f"est. {t_iter:.1f} s per iteration")}
 
 
+def ladder_launch_ms(B, insts, ws, prec, stream, reps):
+    """Average duration of one ladder launch (one instance), HIP events on the launch stream."""
+    import numpy as np
+    import torch
+    ms = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.df_ladder_solve(insts, ws, B.make_opts(prec=prec), stream=stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.mean(ms)) / len(insts)
+
+
+def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None):
+    """Cold (or given) start to tol 1e-8, one instance at a time."""
+    import torch
+    out = []
+    for i, (p, x) in enumerate(zip(problems, insts)):
+        if sigma0 is None:
+            x.sigma.zero_()
+        else:
+            x.sigma.copy_(torch.as_tensor(sigma0[i]))
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        code, it, d = B.df_iterate([x], ws, B.make_opts(prec=prec, mix=0.5, tol=1e-8, max_iter=500,
+                                                        use_graph=graph),
+                                   stream=stream.cuda_stream,
+                                   allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
+        stream.synchronize()
+        out.append({"U": p.U, "iterations": it, "seconds": time.perf_counter() - ta,
+                    "final_diff": d[0], "code": code})
+    return out
+
+
+KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}>", "gjb_o3": "k_ladder_gjb_f64_o3<{np}>",
+                 "vector": "k_ladder_fp64<{np},...>", "mfma": "k_ladder_mfma_f64<{np}>",
+                 "mixed": "k_ladder_mixed<{np}>", "mixed_o3": "k_ladder_mixed_o3<{np}>"}
+
+
+def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
+    flops_launch = 2 * n_om * N * ladder_flops(n_nu)
+    achieved = flops_launch / (lad_ms * 1e-3) / 1e12
+    variant = B.df_ladder_variant(n_nu, prec)
+    kernel_name = KERNEL_SYMBOL[variant].format(np=n_nu)
+    if variant not in ("mixed", "mixed_o3"):
+        peak = FP64_PEAK_TFLOPS
+    else:
+        # executed work: 2 n^3 complex FMA in FP32 (inverse, X gamma) + n^3 in FP64
+        # (residual) per solve; the applicable peak is the time-weighted mix
+        t_unit = 2.0 / FP32_PEAK_TFLOPS + 1.0 / FP64_PEAK_TFLOPS
+        peak = 3.0 / t_unit
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": measured_traffic(kernel_name),
+            "kernel": kernel_name, "variant": variant, "launch_ms": lad_ms,
+            "algorithmic_flops_per_launch": flops_launch}
+
+
+def warm_start_leg(problems, args, log):
+    """Train the warm-start network on the method's own converged Sigma~ at
+    this workload's shape, then predict the three instances' Sigma~."""
+    from paper_1507_00895_amd import warmstart as W
+    p = problems[0]
+    cfg = W.WarmStartConfig(nk=p.nk, n_nu=p.n_nu, n_om=p.n_om, t=p.t)
+    t0 = time.perf_counter()
+    ptrain = W.draw(args.warm_train, 895, cfg)
+    sig, _, _ = W.converge(ptrain, cfg)
+    t_data = time.perf_counter() - t0
+    X = W.build_features(ptrain, cfg)
+    Y = W.targets_from_sigma(sig, cfg)
+    net = W.WarmStartNet(X.shape[1], Y.shape[1])
+    t1 = time.perf_counter()
+    hist = net.fit(X, Y, steps=args.warm_steps)
+    t_train = time.perf_counter() - t1
+    log(f"warm start trained: {args.warm_train} instances ({t_data:.1f} s), "
+        f"{args.warm_steps} steps ({t_train:.1f} s)")
+    params = [(q.U, q.beta) for q in problems]
+    ta = time.perf_counter()
+    pred = net.predict(W.build_features(params, cfg))
+    sigma0 = [W.sigma_from_rows(pred[i * p.N:(i + 1) * p.N], cfg) for i in range(len(problems))]
+    t_inf = (time.perf_counter() - ta) / len(problems)
+    info = {"n_train": args.warm_train, "train_distribution": f"U in {cfg.U_range}, beta in {cfg.beta_range}",
+            "data_seconds": t_data, "train_steps": args.warm_steps, "train_seconds": t_train,
+            "train_loss_first_last": [hist[0][1], hist[-1][1]],
+            "inference_seconds_per_instance": t_inf}
+    return sigma0, info
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -131,6 +231,9 @@ def main():
     from paper_1507_00895_amd import binding as B
     from paper_1507_00895_amd import inputs as I
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     problems = I.workload_square32()
@@ -141,6 +244,16 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
     sh = stream.cuda_stream
+
+    # autotune the ladder kernel for both precisions on this workload's data
+    tuned = {}
+    if not args.no_tune:
+        for name, pr in (("fp64", B.DF_FP64), ("mixed", B.DF_FP32_REFINE)):
+            t_a = time.perf_counter()
+            B.df_autotune(insts, ws, B.make_opts(prec=pr), stream=sh)
+            tuned[name] = {"variant": B.df_ladder_variant(problems[0].n_nu, pr),
+                           "seconds": time.perf_counter() - t_a}
+        log(f"autotuned: {tuned}")
 
     # warmup
     if args.warmup > 0:
@@ -159,28 +272,12 @@ def main():
     assert iters == args.steps
     solves_per_step = sum(2 * p.n_om * p.N for p in problems)
     ms_per_step = 1e3 * dt / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
 
-    # dominant kernel: the ladder, timed with events on the launch stream
-    lad_ms = []
-    for _ in range(max(3, args.steps)):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        B.df_ladder_solve(insts, ws, B.make_opts(prec=prec), stream=sh)
-        e1.record(stream)
-        e1.synchronize()
-        lad_ms.append(e0.elapsed_time(e1))
-    lad_ms = float(np.mean(lad_ms)) / len(insts)        # per launch (one instance)
     p0 = problems[0]
-    flops_launch = 2 * p0.n_om * p0.N * ladder_flops(p0.n_nu)
-    achieved = flops_launch / (lad_ms * 1e-3) / 1e12
-    if prec == B.DF_FP64:
-        peak, kernel_name = FP64_PEAK_TFLOPS, "k_ladder_gjb_f64<64>"
-    else:
-        # executed work: 2 n^3 complex FMA in FP32 (inverse, X gamma) + n^3 in FP64
-        # (residual) per solve; the applicable peak is the time-weighted mix
-        t_unit = 2.0 / FP32_PEAK_TFLOPS + 1.0 / FP64_PEAK_TFLOPS
-        peak, kernel_name = 3.0 / t_unit, "k_ladder_mixed<64>"
+    reps = max(3, args.steps)
+    lad_ms = ladder_launch_ms(B, insts, ws, prec, stream, reps)
+    roof = roofline_of(prec, B, p0.n_om, p0.N, p0.n_nu, lad_ms)
 
     if args.copy_calibration:
         # a plain copy kernel of known size: 256 MiB read + 256 MiB written
@@ -191,20 +288,28 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # seconds per converged Sigma~ (cold start, tol 1e-8), per instance
-    conv = []
+    # the three paths on the same GPU: ladder rate and seconds per converged
+    # Sigma~ (tol 1e-8), per instance
+    paths = {}
     if not args.no_converge:
-        for p, x in zip(problems, insts):
-            x.sigma.zero_()
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            code_c, it_c, d_c = B.df_iterate([x], ws, B.make_opts(prec=prec, mix=0.5, tol=1e-8,
-                                                                  max_iter=500, use_graph=args.graph),
-                                             stream=sh, allow=(B.DF_OK, B.DF_W_FALLBACK,
-                                                               B.DF_E_NOT_CONVERGED))
-            stream.synchronize()
-            conv.append({"U": p.U, "iterations": it_c, "seconds": time.perf_counter() - ta,
-                         "final_diff": d_c[0], "code": code_c})
+        for name, pr in (("fp64", B.DF_FP64), ("mixed", B.DF_FP32_REFINE)):
+            ms = lad_ms if pr == prec else ladder_launch_ms(B, insts, ws, pr, stream, reps)
+            conv = converge_each(B, problems, insts, ws, pr, stream, args.graph)
+            paths[name] = {"ladder_launch_ms": ms,
+                           "ladder_solves_per_s": 2 * p0.n_om * p0.N / (ms * 1e-3),
+                           "roofline_frac": roofline_of(pr, B, p0.n_om, p0.N, p0.n_nu, ms)["frac"],
+                           "s_per_converged_sigma": float(np.mean([c["seconds"] for c in conv])),
+                           "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
+                           "converged": conv}
+            log(f"{name}: {paths[name]['s_per_converged_sigma']:.3f} s per converged Sigma~")
+        if not args.no_warm:
+            sigma0, info = warm_start_leg(problems, args, log)
+            conv = converge_each(B, problems, insts, ws, B.DF_FP64, stream, args.graph, sigma0)
+            sec = float(np.mean([c["seconds"] for c in conv])) + info["inference_seconds_per_instance"]
+            paths["warm_fp64"] = {"s_per_converged_sigma": sec,
+                                  "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
+                                  "converged": conv, "network": info}
+            log(f"warm_fp64: {sec:.3f} s per converged Sigma~")
 
     out = {
         "metric": "ladder (q,omega) solves/s + s per converged Sigma~: FP64 vs FP32-MFMA+refine at 1e-9 rel",
@@ -221,19 +326,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D square 32x32, n_nu 64, n_om 31, beta 20, U in {1,2,4}, t 0.1, "
                                "Hubbard-atom inputs; one step = one outer iteration of all 3",
-                   "path": args.prec, "hip_graph": bool(args.graph),
+                   "path": args.prec, "hip_graph": bool(args.graph), "autotuned": tuned,
                    "solves_per_step": solves_per_step},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(kernel_name),
-                     "kernel": kernel_name,
-                     "launch_ms": lad_ms,
-                     "algorithmic_flops_per_launch": flops_launch},
+        "roofline": roof,
         "ladder_solves_per_s": 2 * p0.n_om * p0.N / (lad_ms * 1e-3),
-        "converged": conv,
+        "paths": paths,
     }
-    if conv:
-        out["s_per_converged_sigma"] = float(np.mean([c["seconds"] for c in conv]))
+    if args.prec in paths:
+        out["s_per_converged_sigma"] = paths[args.prec]["s_per_converged_sigma"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problems)
     print(json.dumps(out), flush=True)

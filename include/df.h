@@ -33,9 +33,10 @@
  * Ownership: the caller allocates every buffer, the workspace included (size
  * it with df_workspace_size; it must be 256-byte aligned).  The library never
  * allocates or frees caller memory; it keeps no state between calls apart
- * from compiled kernels.  Calls are asynchronous on the given stream, except
+ * from compiled kernels and the autotuner's table of ladder kernel choices
+ * (df_autotune).  Calls are asynchronous on the given stream, except
  * df_iterate which synchronises that stream to read back the convergence
- * measure once per iteration.  Calls on distinct workspaces may run
+ * measure once per iteration, and df_autotune.  Calls on distinct workspaces may run
  * concurrently; two calls sharing a workspace must be ordered by the caller.
  *
  * Errors: argument errors are detected on the host and returned before any
@@ -154,6 +155,33 @@ int df_sigma(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
 int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
                int32_t *iters_out, double *diff_out, void *ws, size_t ws_bytes,
                df_stream_t stream);
+
+/* Autotuner for the batched ladder (the hot step of every iteration).  For each
+ * distinct n_nu among the instances (with opts->prec; opts may be NULL =
+ * DF_FP64) it builds that instance's ladder inputs in the workspace (G~ from
+ * sigma, NULL = zero, and chi), times every ladder kernel variant able to run
+ * them (three launches after an untimed one, HIP events on the stream), and
+ * keeps the fastest for later calls of this process.  When the environment
+ * variable DF_TUNE_CACHE names a file, choices are read from it on first use
+ * and the whole table is written back here.  Every variant gives results of
+ * the same precision class (bit patterns may differ between variants).
+ * Synchronous; instance outputs are not touched.  Must not be called while
+ * the stream is being captured (DF_E_INVAL).  The environment variable
+ * DF_LADDER_KERNEL, a variant name, overrides both tuned and default choices. */
+int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, void *ws,
+                size_t ws_bytes, df_stream_t stream);
+
+/* Name of the ladder kernel variant that calls for this n_nu and precision use
+ * now ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3"), written to the
+ * host buffer name (NUL-terminated, name_len bytes at most). */
+int df_ladder_variant(int32_t n_nu, int32_t prec, char *name, size_t name_len);
+
+/* Record a choice by hand, as df_autotune would: later calls for this n_nu and
+ * precision use the named variant.  DF_E_UNSUPPORTED if it cannot serve them. */
+int df_ladder_set_variant(int32_t n_nu, int32_t prec, const char *name);
+
+/* Forget the tuned choices of this process (the cache file is left as is). */
+int df_autotune_reset(void);
 
 /* Static description of a status code. */
 const char *df_strerror(int code);

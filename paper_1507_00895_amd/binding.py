@@ -31,7 +31,8 @@ DF_FP64 = 0
 DF_FP32_REFINE = 1
 
 EXPORTED = ("df_workspace_size", "df_dual_gf", "df_bubble", "df_ladder_solve", "df_sigma",
-            "df_iterate", "df_strerror", "df_version")
+            "df_iterate", "df_autotune", "df_ladder_variant", "df_ladder_set_variant",
+            "df_autotune_reset", "df_strerror", "df_version")
 
 
 class DfInst(ctypes.Structure):
@@ -79,6 +80,11 @@ def load() -> ctypes.CDLL:
                                     ctypes.c_size_t, ctypes.c_void_p]
     lib.df_iterate.argtypes = [P(DfInst), ctypes.c_int32, P(DfOpts), P(ctypes.c_int32),
                                P(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.df_autotune.argtypes = [P(DfInst), ctypes.c_int32, P(DfOpts), ctypes.c_void_p,
+                                ctypes.c_size_t, ctypes.c_void_p]
+    lib.df_ladder_variant.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]
+    lib.df_ladder_set_variant.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p]
+    lib.df_autotune_reset.argtypes = []
     lib.df_strerror.argtypes = [ctypes.c_int]
     lib.df_strerror.restype = ctypes.c_char_p
     lib.df_version.argtypes = []
@@ -248,6 +254,31 @@ def df_iterate(insts, ws, opts: DfOpts, stream=None, allow=(DF_OK, DF_W_FALLBACK
                              diffs, _ptr(ws), ws.numel(), _stream(stream))
     _check("df_iterate", code, ok=allow)
     return code, int(iters.value), list(diffs)
+
+
+def df_autotune(insts, ws, opts: Optional[DfOpts] = None, stream=None):
+    """Time the ladder kernel variants on these instances; keep the fastest (synchronous)."""
+    return _check("df_autotune", load().df_autotune(_arr(insts), len(insts),
+                                                    ctypes.byref(opts) if opts else None,
+                                                    _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def df_ladder_variant(n_nu: int, prec: int = DF_FP64) -> str:
+    buf = ctypes.create_string_buffer(32)
+    _check("df_ladder_variant", load().df_ladder_variant(int(n_nu), int(prec), buf, 32))
+    return buf.value.decode()
+
+
+def df_ladder_set_variant(n_nu: int, prec: int, name: str):
+    return _check("df_ladder_set_variant", load().df_ladder_set_variant(int(n_nu), int(prec),
+                                                                        name.encode()))
+
+
+LADDER_VARIANTS = ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3")
+
+
+def df_autotune_reset():
+    return _check("df_autotune_reset", load().df_autotune_reset())
 
 
 # ---------------------------------------------------------------------------

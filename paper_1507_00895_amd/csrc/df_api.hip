@@ -9,6 +9,7 @@
 
 #include "../../include/df.h"
 #include "df_internal.hpp"
+#include "df_tune.hpp"
 
 using namespace df;
 
@@ -176,57 +177,56 @@ int ensure_attrs() {
 }
 
 // ---- ladder kernel choice ---------------------------------------------------
-// Default: the certified pivot-free blocked kernel on the matrix cores (FP64,
-// or FP32 + FP64 refinement), whose uncertified items go to the
-// partial-pivoting kernel.  DF_LADDER_KERNEL=vector|mfma|gjb overrides the
-// FP64 choice for measurements: vector = partial pivoting with vector FMAs,
-// mfma = partial pivoting with MFMA trailing updates (n_nu <= 64).
-enum LadderKind { LK_GJB = 0, LK_VECTOR = 1, LK_MFMA = 2, LK_MIXED = 3 };
-
-int env_kind() {
-    static int mode = -1;
-    if (mode < 0) {
+// In order: the variant named by DF_LADDER_KERNEL (gjb, gjb_o3, vector, mfma,
+// mixed, mixed_o3) when it serves this n_nu and precision; the autotuner's
+// choice; the default, which is the certified pivot-free blocked kernel on the
+// matrix cores (FP64, or FP32 + FP64 refinement), whose uncertified items go
+// to the partial-pivoting kernel.
+int env_variant() {
+    static int v = -2;
+    if (v == -2) {
         const char *e = getenv("DF_LADDER_KERNEL");
-        mode = LK_GJB;
-        if (e && strcmp(e, "vector") == 0) mode = LK_VECTOR;
-        if (e && strcmp(e, "mfma") == 0) mode = LK_MFMA;
+        v = e ? variant_from_name(e) : -1;
     }
-    return mode;
+    return v;
 }
 
-LadderKind ladder_kind(int n_nu, int prec) {
-    if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(n_nu) != 0) return LK_MIXED;
-    const int mode = env_kind();
-    if (mode == LK_MFMA && ladder_mfma_padded_size(n_nu) != 0) return LK_MFMA;
-    if (mode == LK_GJB && ladder_gjb_padded_size(n_nu) != 0) return LK_GJB;
-    return LK_VECTOR;
+int default_variant(int n_nu, int prec) {
+    if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(n_nu) != 0) return LV_MIXED;
+    if (ladder_gjb_padded_size(n_nu) != 0) return LV_GJB;
+    return LV_VECTOR;
 }
 
-// Instances that share a kernel and its padded size are fused in one launch.
+int ladder_variant(int n_nu, int prec) {
+    const int e = env_variant();
+    if (e >= 0 && variant_supports(e, n_nu, prec)) return e;
+    const int t = tuned_variant(prec, n_nu);
+    if (t >= 0 && variant_supports(t, n_nu, prec)) return t;
+    return default_variant(n_nu, prec);
+}
+
+// Instances that share a kernel build and its padded size are fused in one launch.
 int ladder_class(int n_nu, int prec) {
-    const LadderKind k = ladder_kind(n_nu, prec);
-    int np;
-    switch (k) {
-        case LK_MIXED: np = ladder_mixed_padded_size(n_nu); break;
-        case LK_MFMA: np = ladder_mfma_padded_size(n_nu); break;
-        case LK_GJB: np = ladder_gjb_padded_size(n_nu); break;
-        default: np = ladder_padded_size(n_nu); break;
-    }
-    return (int)k * 256 + np;
+    const int v = ladder_variant(n_nu, prec);
+    return v * 256 + variant_padded_size(v, n_nu);
 }
 
 // Launch the ladder for the items in a (single instance, or a fused table);
 // the certified kernels queue their uncertified items to the pivoting kernel.
-int launch_ladder_kind(LadderKind kind, LadderArgs a, int *queue, int *qcount, hipStream_t st) {
-    switch (kind) {
-        case LK_VECTOR: HIPCHK(launch_ladder_fp64(a, st)); return DF_OK;
-        case LK_MFMA: HIPCHK(launch_ladder_mfma_f64(a, st)); return DF_OK;
+int launch_ladder_variant(int v, LadderArgs a, int *queue, int *qcount, hipStream_t st) {
+    switch (v) {
+        case LV_VECTOR: HIPCHK(launch_ladder_fp64(a, st)); return DF_OK;
+        case LV_MFMA: HIPCHK(launch_ladder_mfma_f64(a, st)); return DF_OK;
         default: break;
     }
     a.queue = queue;
     a.queue_count = qcount;
-    if (kind == LK_MIXED) HIPCHK(launch_ladder_mixed(a, st));
-    else HIPCHK(launch_ladder_gjb_f64(a, st));
+    switch (v) {
+        case LV_MIXED: HIPCHK(launch_ladder_mixed(a, 0, st)); break;
+        case LV_MIXED_O3: HIPCHK(launch_ladder_mixed(a, 3, st)); break;
+        case LV_GJB_O3: HIPCHK(launch_ladder_gjb_f64(a, 3, st)); break;
+        default: HIPCHK(launch_ladder_gjb_f64(a, 0, st)); break;
+    }
     LadderArgs b = a;
     b.queue = nullptr;
     b.queue_count = nullptr;
@@ -339,7 +339,7 @@ int check_opts(const df_opts_t *o, bool need_loop) {
 
 // ---- the fused multi-instance iteration --------------------------------------
 struct FusedClass {
-    LadderKind kind;
+    int variant;
     int n_nu;                         // any member's n_nu (same padded size)
     int t0, t1;                       // table range
     int items;                        // total items of the class
@@ -393,7 +393,7 @@ int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &ac
             d.item0 = c.items;
             c.items += s.items;
             c.n_nu = s.n_nu;
-            c.kind = ladder_kind(s.n_nu, prec);
+            c.variant = ladder_variant(s.n_nu, prec);
             F->table.push_back(d);
             F->active.push_back(i);
         }
@@ -433,7 +433,7 @@ int queue_fused_iteration(const df_inst_t *inst, const Plan &P, const Fused &F,
         a.n_nu = k.n_nu;
         a.item0 = 0;
         a.n_items = k.items;
-        rc = launch_ladder_kind(k.kind, a, at<int>(ws, P.g.queue) + k.queue_off, ints + c, st);
+        rc = launch_ladder_variant(k.variant, a, at<int>(ws, P.g.queue) + k.queue_off, ints + c, st);
         if (rc != DF_OK) return rc;
     }
     for (int i : F.active) {
@@ -561,7 +561,7 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         a.N = s.N;
         a.item0 = 0;
         a.n_items = s.items;
-        rc = launch_ladder_kind(ladder_kind(s.n_nu, prec), a, at<int>(ws, P.g.queue), ints, st);
+        rc = launch_ladder_variant(ladder_variant(s.n_nu, prec), a, at<int>(ws, P.g.queue), ints, st);
         if (rc != DF_OK) return rc;
     }
     return DF_OK;
@@ -697,6 +697,116 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
             if (!(last[i] < opts->tol)) return DF_E_NOT_CONVERGED;
     }
     return any_fallback ? DF_W_FALLBACK : DF_OK;
+}
+
+int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, void *ws,
+                size_t ws_bytes, df_stream_t stream) {
+    int rc = check_opts(opts, false);
+    if (rc != DF_OK) return rc;
+    Plan P;
+    rc = make_plan(inst, n_inst, &P);
+    if (rc != DF_OK) return rc;
+    rc = check_ws(P, ws, ws_bytes);
+    if (rc != DF_OK) return rc;
+    for (int i = 0; i < n_inst; ++i) {
+        const df_inst_t &p = inst[i];
+        if (!p.g || !p.delta || !p.eps || !p.gamma_uu || !p.gamma_ud) return DF_E_INVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess) return DF_E_HIP;
+    if (cap != hipStreamCaptureStatusNone) return DF_E_INVAL;   // timing needs synchronisation
+    rc = ensure_attrs();
+    if (rc != DF_OK) return rc;
+    const int prec = opts ? opts->prec : DF_FP64;
+    int *ints = at<int>(ws, P.g.ints);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return DF_E_HIP;
+    }
+    std::vector<int> done;
+    for (int i = 0; i < n_inst && rc == DF_OK; ++i) {
+        const Shape &s = P.shape[i];
+        bool seen = false;
+        for (int n : done) seen = seen || (n == s.n_nu);
+        if (seen) continue;
+        done.push_back(s.n_nu);
+        // this instance's own ladder inputs, in the workspace
+        const Layout &L = P.lay[i];
+        const size_t b = P.base[i];
+        double *gr = at<double>(ws, b + L.gr);
+        double *gd = at<double>(ws, b + L.gd);
+        double *chi = at<double>(ws, b + L.chi);
+        rc = stage_gamma_prep(inst[i], s, ws, b, L, st);
+        if (rc == DF_OK) rc = stage_dual_gf(inst[i], s, inst[i].sigma, gd, gr, st);
+        if (rc == DF_OK) rc = stage_bubble(inst[i], s, gr, chi, st);
+        if (rc != DF_OK) break;
+        LadderArgs a{};
+        a.gdm = at<double>(ws, b + L.gdm);
+        a.pdm = at<double>(ws, b + L.pdm);
+        a.gtr = at<double>(ws, b + L.gtr);
+        a.chi = chi;
+        a.w = at<double>(ws, b + L.w);
+        a.fallback_count = ints + kMaxClasses + i;
+        a.n_nu = s.n_nu;
+        a.n_om = s.n_om;
+        a.N = s.N;
+        a.item0 = 0;
+        a.n_items = s.items;
+        int best = -1;
+        float best_ms = 0.f;
+        for (int v = 0; v < LV_COUNT && rc == DF_OK; ++v) {
+            if (!variant_supports(v, s.n_nu, prec)) continue;
+            constexpr int kReps = 3;
+            float ms = 0.f;
+            for (int r = 0; r <= kReps && rc == DF_OK; ++r) {   // r = 0: untimed first launch
+                if (r == 1 && hipEventRecord(e0, st) != hipSuccess) rc = DF_E_HIP;
+                if (rc == DF_OK && launch_zero_ints(ints, kMaxClasses + n_inst, st) != hipSuccess)
+                    rc = DF_E_HIP;
+                if (rc == DF_OK) rc = launch_ladder_variant(v, a, at<int>(ws, P.g.queue), ints, st);
+            }
+            if (rc == DF_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = DF_E_HIP;
+            if (rc == DF_OK && (best < 0 || ms < best_ms)) {
+                best = v;
+                best_ms = ms;
+            }
+        }
+        if (rc == DF_OK && best >= 0) set_tuned_variant(prec, s.n_nu, best);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DF_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return DF_E_HIP;
+    return save_tune_cache() == 0 ? DF_OK : DF_E_INVAL;
+}
+
+int df_ladder_variant(int32_t n_nu, int32_t prec, char *name, size_t name_len) {
+    if (!name || name_len == 0) return DF_E_INVAL;
+    if (prec != DF_FP64 && prec != DF_FP32_REFINE) return DF_E_INVAL;
+    if (n_nu < 2 || (n_nu & 1) || n_nu > 128) return DF_E_UNSUPPORTED;
+    const char *v = variant_name(ladder_variant(n_nu, prec));
+    if (strlen(v) + 1 > name_len) return DF_E_INVAL;
+    strcpy(name, v);
+    return DF_OK;
+}
+
+int df_ladder_set_variant(int32_t n_nu, int32_t prec, const char *name) {
+    if (prec != DF_FP64 && prec != DF_FP32_REFINE) return DF_E_INVAL;
+    if (n_nu < 2 || (n_nu & 1) || n_nu > 128) return DF_E_UNSUPPORTED;
+    const int v = variant_from_name(name);
+    if (v < 0) return DF_E_INVAL;
+    if (!variant_supports(v, n_nu, prec)) return DF_E_UNSUPPORTED;
+    set_tuned_variant(prec, n_nu, v);
+    return DF_OK;
+}
+
+int df_autotune_reset(void) {
+    clear_tuned();
+    return DF_OK;
 }
 
 }  // extern "C"

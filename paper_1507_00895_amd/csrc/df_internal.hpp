@@ -120,12 +120,15 @@ hipError_t launch_ladder_fp64(const LadderArgs &a, hipStream_t s);
 // MFMA blocked Gauss-Jordan variant (n_nu <= 64)
 int ladder_mfma_padded_size(int n_nu);
 hipError_t launch_ladder_mfma_f64(const LadderArgs &a, hipStream_t s);
-// certified pivot-free blocked Gauss-Jordan (n_nu <= 128)
+// certified pivot-free blocked Gauss-Jordan (n_nu <= 96); occ = 3 selects the
+// build capped at three waves per SIMD (n_nu <= 64), 0 the compiler's budget
 int ladder_gjb_padded_size(int n_nu);
-hipError_t launch_ladder_gjb_f64(const LadderArgs &a, hipStream_t s);
+bool ladder_gjb_has_occ3(int n_nu);
+hipError_t launch_ladder_gjb_f64(const LadderArgs &a, int occ, hipStream_t s);
 // mixed precision: FP32 certified sweep + one FP64 residual correction (n_nu <= 64)
 int ladder_mixed_padded_size(int n_nu);
-hipError_t launch_ladder_mixed(const LadderArgs &a, hipStream_t s);
+bool ladder_mixed_has_occ3(int n_nu);
+hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, hipStream_t s);
 // pivoting kernel over a device-side queue of items (grid-stride, fixed grid)
 hipError_t launch_ladder_fp64_queue(const LadderArgs &a, int blocks, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);

@@ -16,7 +16,7 @@ constexpr int CERT_ITERS = 6;
 constexpr double CERT_MAX_F64 = 0.999;
 
 template <int NP>
-__global__ __launch_bounds__(NP * 4) void k_ladder_gjb_f64(LadderArgs a0) {
+__device__ __forceinline__ void gjb_body(LadderArgs a0) {
     constexpr int NT = NP / 16;
     typedef MT<double>::v4 d4;
     __shared__ GjShared<double, NP> sh;
@@ -144,8 +144,26 @@ __global__ __launch_bounds__(NP * 4) void k_ladder_gjb_f64(LadderArgs a0) {
     }
 }
 
+// Two register budgets of the same kernel: the compiler's own (two
+// work-groups per CU at NP = 48, 64) and one capped for three waves per SIMD.
 template <int NP>
-static hipError_t launch_gjb(const LadderArgs &a, hipStream_t s) {
+__global__ __launch_bounds__(NP * 4) void k_ladder_gjb_f64(LadderArgs a0) {
+    gjb_body<NP>(a0);
+}
+template <int NP>
+__global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(3, 3)))
+void k_ladder_gjb_f64_o3(LadderArgs a0) {
+    gjb_body<NP>(a0);
+}
+
+template <int NP>
+static hipError_t launch_gjb(const LadderArgs &a, int occ, hipStream_t s) {
+    if constexpr (NP <= 64) {
+        if (occ == 3) {
+            hipLaunchKernelGGL((k_ladder_gjb_f64_o3<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_ladder_gjb_f64<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
     return hipGetLastError();
 }
@@ -160,13 +178,19 @@ int ladder_gjb_padded_size(int n_nu) {
     return 0;   // n_nu = 128 exceeds the register budget of one block-row per wave
 }
 
-hipError_t launch_ladder_gjb_f64(const LadderArgs &a, hipStream_t s) {
+bool ladder_gjb_has_occ3(int n_nu) {
+    const int np = ladder_gjb_padded_size(n_nu);
+    return np != 0 && np <= 64;
+}
+
+hipError_t launch_ladder_gjb_f64(const LadderArgs &a, int occ, hipStream_t s) {
+    if (occ == 3 && !ladder_gjb_has_occ3(a.n_nu)) return hipErrorInvalidValue;
     switch (ladder_gjb_padded_size(a.n_nu)) {
-        case 16: return launch_gjb<16>(a, s);
-        case 32: return launch_gjb<32>(a, s);
-        case 48: return launch_gjb<48>(a, s);
-        case 64: return launch_gjb<64>(a, s);
-        case 96: return launch_gjb<96>(a, s);
+        case 16: return launch_gjb<16>(a, occ, s);
+        case 32: return launch_gjb<32>(a, occ, s);
+        case 48: return launch_gjb<48>(a, occ, s);
+        case 64: return launch_gjb<64>(a, occ, s);
+        case 96: return launch_gjb<96>(a, 0, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -37,7 +37,7 @@ template <int NP> struct MixedShared {
 };
 
 template <int NP>
-__global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a0) {
+__device__ __forceinline__ void mixed_body(LadderArgs a0) {
     constexpr int NT = NP / 16;
     typedef MT<float>::v4 f4;
     typedef MT<double>::v4 d4;
@@ -235,7 +235,23 @@ __global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a0) {
 }
 
 template <int NP>
-static hipError_t launch_mixed(const LadderArgs &a, hipStream_t s) {
+__global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a0) {
+    mixed_body<NP>(a0);
+}
+template <int NP>
+__global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(3, 3)))
+void k_ladder_mixed_o3(LadderArgs a0) {
+    mixed_body<NP>(a0);
+}
+
+template <int NP>
+static hipError_t launch_mixed(const LadderArgs &a, int occ, hipStream_t s) {
+    if constexpr (NP <= 48) {
+        if (occ == 3) {
+            hipLaunchKernelGGL((k_ladder_mixed_o3<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_ladder_mixed<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
     return hipGetLastError();
 }
@@ -249,12 +265,19 @@ int ladder_mixed_padded_size(int n_nu) {
     return 0;   // the FP32 X and Z0 of larger matrices exceed the LDS budget
 }
 
-hipError_t launch_ladder_mixed(const LadderArgs &a, hipStream_t s) {
+// three work-groups per CU fit the LDS only up to NP = 48
+bool ladder_mixed_has_occ3(int n_nu) {
+    const int np = ladder_mixed_padded_size(n_nu);
+    return np != 0 && np <= 48;
+}
+
+hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, hipStream_t s) {
+    if (occ == 3 && !ladder_mixed_has_occ3(a.n_nu)) return hipErrorInvalidValue;
     switch (ladder_mixed_padded_size(a.n_nu)) {
-        case 16: return launch_mixed<16>(a, s);
-        case 32: return launch_mixed<32>(a, s);
-        case 48: return launch_mixed<48>(a, s);
-        case 64: return launch_mixed<64>(a, s);
+        case 16: return launch_mixed<16>(a, occ, s);
+        case 32: return launch_mixed<32>(a, occ, s);
+        case 48: return launch_mixed<48>(a, occ, s);
+        case 64: return launch_mixed<64>(a, 0, s);
         default: return hipErrorInvalidValue;
     }
 }

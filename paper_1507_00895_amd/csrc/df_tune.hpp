@@ -1,0 +1,33 @@
+// Ladder kernel variants and the autotuner's choice table.
+//
+// A variant is one kernel build able to run the batched ladder for a given
+// n_nu and precision.  The table maps (precision, n_nu) to the variant the
+// autotuner measured fastest; it lives for the process and, when the
+// environment variable DF_TUNE_CACHE names a file, is read from and written to
+// that file (one "prec n_nu name" line per entry).
+#pragma once
+
+namespace df {
+
+enum LadderVariant {
+    LV_GJB = 0,        // certified blocked Gauss-Jordan, FP64 MFMA, compiler's register budget
+    LV_GJB_O3 = 1,     // same, capped for three waves per SIMD
+    LV_VECTOR = 2,     // partial pivoting, FP64 vector FMAs
+    LV_MFMA = 3,       // partial pivoting, FP64 MFMA trailing updates
+    LV_MIXED = 4,      // certified FP32 sweep + FP64 residual correction
+    LV_MIXED_O3 = 5,   // same, capped for three waves per SIMD
+    LV_COUNT = 6
+};
+
+const char *variant_name(int v);
+int variant_from_name(const char *name);          // -1 if unknown
+bool variant_supports(int v, int n_nu, int prec);   // kernel exists for this n_nu and precision
+int variant_padded_size(int v, int n_nu);
+
+// tuned choice for (prec, n_nu), or -1
+int tuned_variant(int prec, int n_nu);
+void set_tuned_variant(int prec, int n_nu, int v);
+void clear_tuned();
+int save_tune_cache();   // 0 on success or when no cache file is configured
+
+}  // namespace df

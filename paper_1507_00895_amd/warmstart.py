@@ -12,12 +12,14 @@ inference from df_mlp_loss_grad / df_mlp_adam / df_mlp_forward.  torch holds
 device buffers and does index bookkeeping (minibatch gathers, reshapes).
 
 Features (one row per k point of an instance; 2D square lattices):
-  * instance: U, beta, t, D (standardised over the training set);
+  * instance: U, beta, log U, log beta, 1/beta, t, D (standardised over the
+    training set);
   * k: five point-group-invariant combinations of cos k_i and cos 2k_i;
   * coarse dual propagator: G~0 of the instance on an 8 x 8 grid at the four
     lowest positive Matsubara frequencies, at the 15 points of the irreducible
     wedge 0 <= k_y <= k_x <= pi (real and imaginary parts: 120 numbers).
 Targets: Re and Im of the converged Sigma~(k, nu_n), n = 0 .. n_nu/2 - 1,
+divided by the instance's rms |Sigma~|, plus the log of that scale;
 standardised per output.
 """
 from __future__ import annotations
@@ -51,8 +53,16 @@ class WarmStartConfig:
 
 
 def draw(n: int, seed: int, cfg: WarmStartConfig):
+    """n (U, beta) pairs, Latin-hypercube stratified over the two ranges."""
     rng = np.random.default_rng(seed)
-    return [(float(rng.uniform(*cfg.U_range)), float(rng.uniform(*cfg.beta_range))) for _ in range(n)]
+    out = []
+    cols = []
+    for lo, hi in (cfg.U_range, cfg.beta_range):
+        u = (rng.permutation(n) + rng.uniform(size=n)) / n
+        cols.append(lo + (hi - lo) * u)
+    for U, beta in zip(*cols):
+        out.append((float(U), float(beta)))
+    return out
 
 
 # ---------------------------------------------------------------- features
@@ -91,13 +101,13 @@ def coarse_gd0(params: List[tuple], cfg: WarmStartConfig, device="cuda") -> np.n
 
 
 def build_features(params: List[tuple], cfg: WarmStartConfig, device="cuda") -> np.ndarray:
-    """[n * N, 129] feature rows, instance-major."""
+    """[n * N, 132] feature rows, instance-major."""
     N = cfg.nk ** 2
     kf = k_features(cfg.nk)
     g0 = coarse_gd0(params, cfg, device)
     rows = []
     for (U, beta), gsum in zip(params, g0):
-        inst = np.array([U, beta, cfg.t, 2.0])
+        inst = np.array([U, beta, math.log(U), math.log(beta), 1.0 / beta, cfg.t, 2.0])
         rows.append(np.concatenate([np.tile(inst, (N, 1)), kf, np.tile(gsum, (N, 1))], axis=1))
     return np.concatenate(rows, axis=0)
 
@@ -134,19 +144,29 @@ def converge(params: List[tuple], cfg: WarmStartConfig, sigma0: Optional[list] =
 
 
 def targets_from_sigma(sigmas, cfg: WarmStartConfig) -> np.ndarray:
-    """[n * N, n_nu] rows: Re and Im of Sigma~ at the positive frequencies."""
+    """[n * N, 3 n_nu / 2] rows: Re and Im of Sigma~ / S at the positive
+    frequencies, then n_nu / 2 copies of log S, with S the instance's
+    root-mean-square |Sigma~|.
+
+    Sigma~ spans orders of magnitude over the (U, beta) range; splitting off
+    the instance scale makes the regression error relative.  The copies give
+    the scale the same weight in the mean squared error as the shape.
+    """
     h = cfg.n_nu // 2
     rows = []
     for s in sigmas:
-        pos = s[h:].T                                              # [N, h], nu_0 .. nu_{h-1}
-        rows.append(np.concatenate([pos.real, pos.imag], axis=1))
+        S = max(float(np.sqrt(np.mean(np.abs(s) ** 2))), 1e-300)
+        pos = s[h:].T / S                                          # [N, h], nu_0 .. nu_{h-1}
+        rows.append(np.concatenate([pos.real, pos.imag, np.full((pos.shape[0], h), math.log(S))],
+                                   axis=1))
     return np.concatenate(rows, axis=0)
 
 
 def sigma_from_rows(rows: np.ndarray, cfg: WarmStartConfig) -> np.ndarray:
     """Inverse of targets_from_sigma for one instance, with Sigma~(-nu) = Sigma~(nu)*."""
     h = cfg.n_nu // 2
-    pos = (rows[:, :h] + 1j * rows[:, h:]).T                        # [h, N]
+    S = math.exp(float(np.mean(rows[:, 2 * h:])))
+    pos = S * (rows[:, :h] + 1j * rows[:, h:2 * h]).T               # [h, N]
     return np.concatenate([np.conj(pos[::-1]), pos], axis=0)
 
 
@@ -212,22 +232,31 @@ class WarmStartNet:
 
 def train_and_evaluate(n_train: int = 256, n_test: int = 16, steps: int = 2000,
                        cfg: Optional[WarmStartConfig] = None, seed_train: int = 895,
-                       seed_test: int = 896, device="cuda"):
-    """Generate converged Sigma~ with the method, train, compare cold and warm starts."""
+                       seed_test: int = 896, test_params: Optional[List[tuple]] = None,
+                       device="cuda", log=None):
+    """Generate converged Sigma~ with the method, train, compare cold and warm starts.
+
+    test_params: explicit (U, beta) pairs to evaluate on (default: n_test draws).
+    log: optional callable receiving progress strings.
+    """
+    log = log or (lambda msg: None)
     cfg = cfg or WarmStartConfig()
     N = cfg.nk ** 2
     t0 = time.perf_counter()
     ptrain = draw(n_train, seed_train, cfg)
     sig, its_train, _ = converge(ptrain, cfg, device=device)
     t_data = time.perf_counter() - t0
+    log(f"warm start: {n_train} converged training instances in {t_data:.1f} s")
     X = build_features(ptrain, cfg, device)
     Y = targets_from_sigma(sig, cfg)
     net = WarmStartNet(X.shape[1], Y.shape[1], device=device)
     t1 = time.perf_counter()
     hist = net.fit(X, Y, steps=steps)
     t_train = time.perf_counter() - t1
+    log(f"warm start: {steps} training steps in {t_train:.1f} s, loss {hist[0][1]:.3g} -> {hist[-1][1]:.3g}")
 
-    ptest = draw(n_test, seed_test, cfg)
+    ptest = list(test_params) if test_params is not None else draw(n_test, seed_test, cfg)
+    n_test = len(ptest)
     ta = time.perf_counter()
     Xt = build_features(ptest, cfg, device)
     pred = net.predict(Xt)
@@ -240,7 +269,7 @@ def train_and_evaluate(n_train: int = 256, n_test: int = 16, steps: int = 2000,
     return {
         "workload": f"2D {cfg.nk}x{cfg.nk}, n_nu {cfg.n_nu}, n_om {cfg.n_om}, t {cfg.t}, "
                     f"U in {cfg.U_range}, beta in {cfg.beta_range}, tol {cfg.tol}",
-        "n_train": n_train, "n_test": n_test, "train_steps": steps,
+        "n_train": n_train, "n_test": n_test, "train_steps": steps, "test_params": ptest,
         "train_loss_first_last": [hist[0][1], hist[-1][1]],
         "seconds_data": t_data, "seconds_train": t_train, "seconds_inference": t_inf,
         "iterations_cold": it_cold, "iterations_warm": it_warm,

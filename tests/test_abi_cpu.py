@@ -137,3 +137,32 @@ def test_mlp_host_validation():
     assert lib.df_mlp_adam(0, fake, fake, fake, fake, 1, 1e-3, None) == B.DF_E_INVAL
     assert lib.df_mlp_adam(10, fake, fake, fake, fake, 0, 1e-3, None) == B.DF_E_INVAL
     assert lib.df_mlp_adam(10, fake, fake, fake, fake, 1, 0.0, None) == B.DF_E_INVAL
+
+
+def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
+    B.df_autotune_reset()
+    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb"
+    assert B.df_ladder_variant(64, B.DF_FP32_REFINE) == "mixed"
+    assert B.df_ladder_variant(96, B.DF_FP32_REFINE) == "gjb"      # beyond the mixed kernel
+    assert B.df_ladder_variant(128, B.DF_FP64) == "vector"
+    B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o3")
+    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3"
+    assert B.df_ladder_variant(62, B.DF_FP64) == "gjb"               # keyed by exact n_nu
+    for bad in [(96, B.DF_FP64, "gjb_o3"), (128, B.DF_FP64, "gjb"), (64, B.DF_FP64, "mixed"),
+                (64, B.DF_FP32_REFINE, "vector"), (64, B.DF_FP32_REFINE, "mixed_o3")]:
+        with pytest.raises(B.DfError) as e:
+            B.df_ladder_set_variant(*bad)
+        assert e.value.code == B.DF_E_UNSUPPORTED
+    with pytest.raises(B.DfError):
+        B.df_ladder_set_variant(64, B.DF_FP64, "nonsense")
+    with pytest.raises(B.DfError):
+        B.df_ladder_variant(130, B.DF_FP64)
+    B.df_autotune_reset()
+    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb"
+
+
+def test_autotune_validates_before_any_gpu_work():
+    lib = B.load()
+    assert lib.df_autotune(None, 1, None, None, 0, None) == B.DF_E_INVAL
+    arr = (B.DfInst * 1)(_inst())
+    assert lib.df_autotune(arr, 1, None, None, 0, None) == B.DF_E_WORKSPACE

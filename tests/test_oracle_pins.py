@@ -382,5 +382,6 @@ def test_warmstart_target_layout_round_trip():
     pos = rng.standard_normal((4, 16)) + 1j * rng.standard_normal((4, 16))
     sig = np.concatenate([np.conj(pos[::-1]), pos], axis=0)          # Sigma(-nu) = Sigma(nu)*
     rows = W.targets_from_sigma([sig], cfg)
-    assert rows.shape == (16, 8)
-    assert np.array_equal(W.sigma_from_rows(rows, cfg), sig)
+    assert rows.shape == (16, 12)
+    assert np.allclose(W.sigma_from_rows(rows, cfg), sig, rtol=1e-14, atol=0)
+    assert np.allclose(rows[:, 8:], np.log(np.sqrt(np.mean(np.abs(sig) ** 2))))
