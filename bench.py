@@ -1,6 +1,6 @@
 """Benchmark of the ladder dual-fermion hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|mixed|fp32]
                     [--no-cpu-baseline] [--no-converge] [--no-warm]
 
 Workload: 2D square lattice 32x32, n_nu = 64, n_om = 31, beta = 20,
@@ -12,10 +12,12 @@ three instances.  Inputs are resident in HBM before the timed region.
 Prints one JSON line.  value = (q, Om, channel) ladder solves per second of
 whole iterations of the --prec path; beside it: the ladder kernel's own rate
 and roofline, and under "paths" the ladder rate and seconds per converged
-Sigma~ (tol 1e-8) of the plain FP64 path, the mixed-precision path and the
-FP64 path warm-started by the learned network (trained inside the run on
-converged Sigma~ of the same shape; its cost is reported separately), and
-the CPU oracle rate.  Progress goes to stderr.
+Sigma~ (tol 1e-8) of the plain FP64 path, the per-ladder mixed-precision
+path (FP32 + FP64 residual correction), the adaptive path (FP32 ladders while
+the diff exceeds 1e-4, FP64 after), and both FP64 and adaptive paths
+warm-started by the learned network (trained inside the run on converged
+Sigma~ of the same shape; its cost is reported separately), and the CPU
+oracle rate.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -69,7 +71,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--prec", choices=["fp64", "mixed", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true",
                     help="skip the seconds-per-converged-Sigma~ legs of all paths")
@@ -147,7 +149,8 @@ def ladder_launch_ms(B, insts, ws, prec, stream, reps):
 
 
 def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None):
-    """Cold (or given) start to tol 1e-8, one instance at a time."""
+    """Cold (or given) start to tol 1e-8, one instance at a time (DF_ADAPTIVE:
+    FP32 ladders down to a diff of 1e-4, FP64 after)."""
     import torch
     out = []
     for i, (p, x) in enumerate(zip(problems, insts)):
@@ -158,7 +161,7 @@ def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None):
         torch.cuda.synchronize()
         ta = time.perf_counter()
         code, it, d = B.df_iterate([x], ws, B.make_opts(prec=prec, mix=0.5, tol=1e-8, max_iter=500,
-                                                        use_graph=graph),
+                                                        use_graph=graph, switch_tol=1e-4),
                                    stream=stream.cuda_stream,
                                    allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
         stream.synchronize()
@@ -169,7 +172,8 @@ def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None):
 
 KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}>", "gjb_o3": "k_ladder_gjb_f64_o3<{np}>",
                  "vector": "k_ladder_fp64<{np},...>", "mfma": "k_ladder_mfma_f64<{np}>",
-                 "mixed": "k_ladder_mixed<{np}>", "mixed_o3": "k_ladder_mixed_o3<{np}>"}
+                 "mixed": "k_ladder_mixed<{np}>", "mixed_o3": "k_ladder_mixed_o3<{np}>",
+                 "fp32": "k_ladder_fp32<{np}>", "fp32_o4": "k_ladder_fp32_o4<{np}>"}
 
 
 def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
@@ -177,7 +181,9 @@ def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
     achieved = flops_launch / (lad_ms * 1e-3) / 1e12
     variant = B.df_ladder_variant(n_nu, prec)
     kernel_name = KERNEL_SYMBOL[variant].format(np=n_nu)
-    if variant not in ("mixed", "mixed_o3"):
+    if variant in ("fp32", "fp32_o4"):
+        peak = FP32_PEAK_TFLOPS
+    elif variant not in ("mixed", "mixed_o3"):
         peak = FP64_PEAK_TFLOPS
     else:
         # executed work: 2 n^3 complex FMA in FP32 (inverse, X gamma) + n^3 in FP64
@@ -238,7 +244,7 @@ def main():
     dev = torch.device("cuda:0")
     problems = I.workload_square32()
     insts = [B.make_instance(p, device=dev) for p in problems]
-    prec = B.DF_FP64 if args.prec == "fp64" else B.DF_FP32_REFINE
+    prec = {"fp64": B.DF_FP64, "mixed": B.DF_FP32_REFINE, "fp32": B.DF_FP32}[args.prec]
     opts = B.make_opts(prec=prec, mix=0.5, tol=0.0, max_iter=1, use_graph=args.graph)
     ws = B.workspace(insts, opts, device=dev)
     stream = torch.cuda.Stream(device=dev)
@@ -248,7 +254,7 @@ def main():
     # autotune the ladder kernel for both precisions on this workload's data
     tuned = {}
     if not args.no_tune:
-        for name, pr in (("fp64", B.DF_FP64), ("mixed", B.DF_FP32_REFINE)):
+        for name, pr in (("fp64", B.DF_FP64), ("mixed", B.DF_FP32_REFINE), ("fp32", B.DF_FP32)):
             t_a = time.perf_counter()
             B.df_autotune(insts, ws, B.make_opts(prec=pr), stream=sh)
             tuned[name] = {"variant": B.df_ladder_variant(problems[0].n_nu, pr),
@@ -292,24 +298,31 @@ def main():
     # Sigma~ (tol 1e-8), per instance
     paths = {}
     if not args.no_converge:
-        for name, pr in (("fp64", B.DF_FP64), ("mixed", B.DF_FP32_REFINE)):
-            ms = lad_ms if pr == prec else ladder_launch_ms(B, insts, ws, pr, stream, reps)
-            conv = converge_each(B, problems, insts, ws, pr, stream, args.graph)
-            paths[name] = {"ladder_launch_ms": ms,
-                           "ladder_solves_per_s": 2 * p0.n_om * p0.N / (ms * 1e-3),
-                           "roofline_frac": roofline_of(pr, B, p0.n_om, p0.N, p0.n_nu, ms)["frac"],
-                           "s_per_converged_sigma": float(np.mean([c["seconds"] for c in conv])),
-                           "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
-                           "converged": conv}
-            log(f"{name}: {paths[name]['s_per_converged_sigma']:.3f} s per converged Sigma~")
+        for name, pr in (("fp64", B.DF_FP64), ("mixed", B.DF_FP32_REFINE), ("fp32", B.DF_FP32),
+                         ("adaptive", B.DF_ADAPTIVE)):
+            entry = {}
+            if pr != B.DF_ADAPTIVE:
+                ms = lad_ms if pr == prec else ladder_launch_ms(B, insts, ws, pr, stream, reps)
+                entry = {"ladder_variant": B.df_ladder_variant(p0.n_nu, pr), "ladder_launch_ms": ms,
+                         "ladder_solves_per_s": 2 * p0.n_om * p0.N / (ms * 1e-3),
+                         "roofline_frac": roofline_of(pr, B, p0.n_om, p0.N, p0.n_nu, ms)["frac"]}
+            if pr != B.DF_FP32:       # FP32 alone does not reach the FP64 fixed point
+                conv = converge_each(B, problems, insts, ws, pr, stream, args.graph)
+                entry.update({"s_per_converged_sigma": float(np.mean([c["seconds"] for c in conv])),
+                              "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
+                              "converged": conv})
+                log(f"{name}: {entry['s_per_converged_sigma']:.3f} s per converged Sigma~")
+            paths[name] = entry
         if not args.no_warm:
             sigma0, info = warm_start_leg(problems, args, log)
-            conv = converge_each(B, problems, insts, ws, B.DF_FP64, stream, args.graph, sigma0)
-            sec = float(np.mean([c["seconds"] for c in conv])) + info["inference_seconds_per_instance"]
-            paths["warm_fp64"] = {"s_per_converged_sigma": sec,
-                                  "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
-                                  "converged": conv, "network": info}
-            log(f"warm_fp64: {sec:.3f} s per converged Sigma~")
+            for name, pr in (("warm_fp64", B.DF_FP64), ("warm_adaptive", B.DF_ADAPTIVE)):
+                conv = converge_each(B, problems, insts, ws, pr, stream, args.graph, sigma0)
+                sec = float(np.mean([c["seconds"] for c in conv])) + info["inference_seconds_per_instance"]
+                paths[name] = {"s_per_converged_sigma": sec,
+                               "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
+                               "converged": conv}
+                log(f"{name}: {sec:.3f} s per converged Sigma~")
+            paths["warm_network"] = info
 
     out = {
         "metric": "ladder (q,omega) solves/s + s per converged Sigma~: FP64 vs FP32-MFMA+refine at 1e-9 rel",
@@ -322,7 +335,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == B.DF_FP64 else "f32+f64",
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "fp32": "f32"}[args.prec],
         "data": "synthetic",
         "config": {"workload": "2D square 32x32, n_nu 64, n_om 31, beta 20, U in {1,2,4}, t 0.1, "
                                "Hubbard-atom inputs; one step = one outer iteration of all 3",

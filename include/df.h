@@ -70,6 +70,9 @@ extern "C" {
 /* ladder precision */
 #define DF_FP64              0   /* plain FP64 inversion                          */
 #define DF_FP32_REFINE       1   /* FP32 inversion + FP64 residual refinement     */
+#define DF_FP32              2   /* FP32 inversion alone (relative error ~1e-6)   */
+#define DF_ADAPTIVE          3   /* df_iterate only: DF_FP32 ladders while an
+                                    instance's last diff >= switch_tol, then DF_FP64 */
 
 typedef void *df_stream_t;      /* hipStream_t; NULL is the null stream */
 
@@ -106,21 +109,27 @@ typedef struct {
 
 /*
  * Options.
- *   prec        DF_FP64 or DF_FP32_REFINE
- *   max_refine  refinement steps of the FP32 path (1..4); ignored for DF_FP64
+ *   prec        DF_FP64, DF_FP32_REFINE, DF_FP32, or (df_iterate) DF_ADAPTIVE
+ *   max_iter    iteration limit of df_iterate, >= 1
  *   mix         weight alpha of the new Sigma~ in the linear mixing, (0, 1]
  *   tol         df_iterate stops once ||Sigma_new - Sigma_old||_F / ||Sigma_new||_F < tol
  *               (every instance); tol <= 0 runs exactly max_iter iterations
- *   max_iter    iteration limit of df_iterate, >= 1
+ *   switch_tol  DF_ADAPTIVE: diff below which an instance's ladders switch from
+ *               FP32 to FP64 (<= 0: 1e-4).  The FP32 ladders' error (~1e-6
+ *               relative) then lies below the iterate's own distance to the
+ *               fixed point, and the FP64 iterations that follow contract it
+ *               away with the rest, so the converged Sigma~ is that of DF_FP64.
  *   use_graph   nonzero: df_iterate captures one iteration in a hipGraph and replays it
+ *   reserved    zero
  */
 typedef struct {
     int32_t prec;
-    int32_t max_refine;
+    int32_t max_iter;
     double mix;
     double tol;
-    int32_t max_iter;
+    double switch_tol;
     int32_t use_graph;
+    int32_t reserved;
 } df_opts_t;
 
 /* Workspace bytes needed by any entry point for these instances and options. */
@@ -137,8 +146,8 @@ int df_bubble(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
 
 /* eqs. (spin_symm), (dual_ladder), (lin_alg_inv) and the radius test; Gamma^(2) of
  * eq. (sd).  Reads gamma_uu, gamma_ud, chi.  Writes w and, when non-NULL, logdet
- * and status.  opts may be NULL (DF_FP64).  Returns DF_OK; the per-ladder
- * outcome is in status. */
+ * and status.  opts may be NULL (DF_FP64); DF_ADAPTIVE is rejected here
+ * (DF_E_INVAL).  Returns DF_OK; the per-ladder outcome is in status. */
 int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
                     void *ws, size_t ws_bytes, df_stream_t stream);
 
@@ -158,7 +167,7 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
 
 /* Autotuner for the batched ladder (the hot step of every iteration).  For each
  * distinct n_nu among the instances (with opts->prec; opts may be NULL =
- * DF_FP64) it builds that instance's ladder inputs in the workspace (G~ from
+ * DF_FP64; DF_ADAPTIVE tunes both of its precisions) it builds that instance's ladder inputs in the workspace (G~ from
  * sigma, NULL = zero, and chi), times every ladder kernel variant able to run
  * them (three launches after an untimed one, HIP events on the stream), and
  * keeps the fastest for later calls of this process.  When the environment
@@ -172,7 +181,8 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
                 size_t ws_bytes, df_stream_t stream);
 
 /* Name of the ladder kernel variant that calls for this n_nu and precision use
- * now ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3"), written to the
+ * now ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4"),
+ * for prec DF_FP64, DF_FP32_REFINE or DF_FP32, written to the
  * host buffer name (NUL-terminated, name_len bytes at most). */
 int df_ladder_variant(int32_t n_nu, int32_t prec, char *name, size_t name_len);
 

@@ -29,6 +29,8 @@ DF_W_FALLBACK = 1
 
 DF_FP64 = 0
 DF_FP32_REFINE = 1
+DF_FP32 = 2
+DF_ADAPTIVE = 3
 
 EXPORTED = ("df_workspace_size", "df_dual_gf", "df_bubble", "df_ladder_solve", "df_sigma",
             "df_iterate", "df_autotune", "df_ladder_variant", "df_ladder_set_variant",
@@ -49,8 +51,9 @@ class DfInst(ctypes.Structure):
 
 class DfOpts(ctypes.Structure):
     _fields_ = [
-        ("prec", ctypes.c_int32), ("max_refine", ctypes.c_int32), ("mix", ctypes.c_double),
-        ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+        ("prec", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("mix", ctypes.c_double),
+        ("tol", ctypes.c_double), ("switch_tol", ctypes.c_double), ("use_graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -191,8 +194,9 @@ def _arr(insts: Sequence[Instance]):
     return arr
 
 
-def _opts(prec=DF_FP64, max_refine=2, mix=0.5, tol=0.0, max_iter=10, use_graph=0) -> DfOpts:
-    return DfOpts(int(prec), int(max_refine), float(mix), float(tol), int(max_iter), int(use_graph))
+def _opts(prec=DF_FP64, mix=0.5, tol=0.0, max_iter=10, use_graph=0, switch_tol=0.0) -> DfOpts:
+    return DfOpts(int(prec), int(max_iter), float(mix), float(tol), float(switch_tol),
+                  int(use_graph), 0)
 
 
 def make_opts(**kw) -> DfOpts:
@@ -274,7 +278,7 @@ def df_ladder_set_variant(n_nu: int, prec: int, name: str):
                                                                         name.encode()))
 
 
-LADDER_VARIANTS = ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3")
+LADDER_VARIANTS = ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4")
 
 
 def df_autotune_reset():

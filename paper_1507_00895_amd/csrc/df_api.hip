@@ -193,6 +193,7 @@ int env_variant() {
 
 int default_variant(int n_nu, int prec) {
     if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(n_nu) != 0) return LV_MIXED;
+    if (prec == DF_FP32 && ladder_mixed_padded_size(n_nu) != 0) return LV_FP32;
     if (ladder_gjb_padded_size(n_nu) != 0) return LV_GJB;
     return LV_VECTOR;
 }
@@ -222,6 +223,8 @@ int launch_ladder_variant(int v, LadderArgs a, int *queue, int *qcount, hipStrea
     a.queue = queue;
     a.queue_count = qcount;
     switch (v) {
+        case LV_FP32: HIPCHK(launch_ladder_fp32(a, 0, st)); break;
+        case LV_FP32_O4: HIPCHK(launch_ladder_fp32(a, 4, st)); break;
         case LV_MIXED: HIPCHK(launch_ladder_mixed(a, 0, st)); break;
         case LV_MIXED_O3: HIPCHK(launch_ladder_mixed(a, 3, st)); break;
         case LV_GJB_O3: HIPCHK(launch_ladder_gjb_f64(a, 3, st)); break;
@@ -325,10 +328,13 @@ int stage_reduce_mix(const Shape &s, const double *part, double *sigma_calc, dou
     return DF_OK;
 }
 
-int check_opts(const df_opts_t *o, bool need_loop) {
+bool ladder_prec(int prec) { return prec == DF_FP64 || prec == DF_FP32_REFINE || prec == DF_FP32; }
+
+// need_loop: df_iterate's fields are checked too; adaptive: DF_ADAPTIVE allowed
+int check_opts(const df_opts_t *o, bool need_loop, bool adaptive) {
     if (!o) return need_loop ? DF_E_INVAL : DF_OK;
-    if (o->prec != DF_FP64 && o->prec != DF_FP32_REFINE) return DF_E_INVAL;
-    if (o->prec == DF_FP32_REFINE && (o->max_refine < 1 || o->max_refine > 4)) return DF_E_INVAL;
+    if (!ladder_prec(o->prec) && !(adaptive && o->prec == DF_ADAPTIVE)) return DF_E_INVAL;
+    if (o->reserved != 0 || !isfinite(o->switch_tol)) return DF_E_INVAL;
     if (need_loop) {
         if (!(o->mix > 0.0 && o->mix <= 1.0)) return DF_E_INVAL;
         if (o->max_iter < 1) return DF_E_INVAL;
@@ -354,14 +360,14 @@ struct Fused {
 
 // Group the active instances by ladder class and write the device table.
 // Ordinary (not captured) stream work, synchronised before returning.
-int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &act, int prec,
-                void *ws, Fused *F, hipStream_t st) {
+int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &act,
+                const std::vector<int> &prec, void *ws, Fused *F, hipStream_t st) {
     F->active.clear();
     F->cls.clear();
     F->table.clear();
     std::vector<int> keys;
     for (int i : act) {
-        const int key = ladder_class(P.shape[i].n_nu, prec);
+        const int key = ladder_class(P.shape[i].n_nu, prec[i]);
         bool seen = false;
         for (int k : keys) seen = seen || (k == key);
         if (!seen) keys.push_back(key);
@@ -374,7 +380,7 @@ int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &ac
         c.items = 0;
         c.queue_off = qoff;
         for (int i : act) {
-            if (ladder_class(P.shape[i].n_nu, prec) != key) continue;
+            if (ladder_class(P.shape[i].n_nu, prec[i]) != key) continue;
             const Shape &s = P.shape[i];
             const Layout &L = P.lay[i];
             const size_t b = P.base[i];
@@ -393,7 +399,7 @@ int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &ac
             d.item0 = c.items;
             c.items += s.items;
             c.n_nu = s.n_nu;
-            c.variant = ladder_variant(s.n_nu, prec);
+            c.variant = ladder_variant(s.n_nu, prec[i]);
             F->table.push_back(d);
             F->active.push_back(i);
         }
@@ -474,7 +480,7 @@ const char *df_strerror(int code) {
 
 int df_workspace_size(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, size_t *bytes) {
     if (!bytes) return DF_E_INVAL;
-    int rc = check_opts(opts, false);
+    int rc = check_opts(opts, false, true);
     if (rc != DF_OK) return rc;
     Plan P;
     rc = make_plan(inst, n_inst, &P);
@@ -525,7 +531,7 @@ int df_bubble(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes, 
 
 int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, void *ws,
                     size_t ws_bytes, df_stream_t stream) {
-    int rc = check_opts(opts, false);
+    int rc = check_opts(opts, false, false);
     if (rc != DF_OK) return rc;
     Plan P;
     rc = make_plan(inst, n_inst, &P);
@@ -596,7 +602,7 @@ int df_sigma(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes, d
 
 int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int32_t *iters_out,
                double *diff_out, void *ws, size_t ws_bytes, df_stream_t stream) {
-    int rc = check_opts(opts, true);
+    int rc = check_opts(opts, true, true);
     if (rc != DF_OK) return rc;
     Plan P;
     rc = make_plan(inst, n_inst, &P);
@@ -627,6 +633,12 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     std::vector<double> last(n_inst, INFINITY);
     std::vector<double> hdiff(2 * (size_t)n_inst);
     std::vector<int> hints(kMaxClasses + n_inst);
+    // ladder precision of each instance; DF_ADAPTIVE starts in FP32 and moves
+    // an instance to FP64 (for good) once its diff falls below switch_tol
+    const bool adaptive = opts->prec == DF_ADAPTIVE;
+    const double switch_tol = opts->switch_tol > 0.0 ? opts->switch_tol : 1e-4;
+    std::vector<int> cur(n_inst, adaptive ? DF_FP32 : opts->prec);
+    std::vector<double> last_prev(n_inst, INFINITY);
     Fused F;
     bool rebuild = true;
     int it = 0;
@@ -635,7 +647,7 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     while (it < opts->max_iter && !act.empty()) {
         if (rebuild) {
             cleanup();
-            rc = build_fused(inst, P, act, opts->prec, ws, &F, st);
+            rc = build_fused(inst, P, act, cur, ws, &F, st);
             if (rc != DF_OK) return rc;
             if (graph) {
                 hipGraph_t g = nullptr;
@@ -680,6 +692,19 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
                 result = DF_E_NONFINITE;
                 continue;
             }
+            // move to FP64 below switch_tol, at tol (an instance converges
+            // only on FP64 ladders), or when the FP32 iteration stops
+            // contracting (its rounding floor)
+            const double prev = last_prev[i];
+            last_prev[i] = hdiff[2 * i];
+            if (adaptive && cur[i] == DF_FP32 &&
+                (hdiff[2 * i] < switch_tol || (opts->tol > 0.0 && hdiff[2 * i] < opts->tol) ||
+                 hdiff[2 * i] > 0.95 * prev)) {
+                cur[i] = DF_FP64;
+                rebuild = true;
+                next.push_back(i);
+                continue;
+            }
             if (opts->tol > 0.0 && hdiff[2 * i] < opts->tol) continue;
             next.push_back(i);
         }
@@ -701,7 +726,7 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
 
 int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, void *ws,
                 size_t ws_bytes, df_stream_t stream) {
-    int rc = check_opts(opts, false);
+    int rc = check_opts(opts, false, true);
     if (rc != DF_OK) return rc;
     Plan P;
     rc = make_plan(inst, n_inst, &P);
@@ -718,7 +743,9 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
     if (cap != hipStreamCaptureStatusNone) return DF_E_INVAL;   // timing needs synchronisation
     rc = ensure_attrs();
     if (rc != DF_OK) return rc;
-    const int prec = opts ? opts->prec : DF_FP64;
+    std::vector<int> precs;
+    if (opts && opts->prec == DF_ADAPTIVE) precs = {DF_FP32, DF_FP64};
+    else precs = {opts ? opts->prec : DF_FP64};
     int *ints = at<int>(ws, P.g.ints);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -754,6 +781,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         a.N = s.N;
         a.item0 = 0;
         a.n_items = s.items;
+        for (int prec : precs) {
         int best = -1;
         float best_ms = 0.f;
         for (int v = 0; v < LV_COUNT && rc == DF_OK; ++v) {
@@ -776,6 +804,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
             }
         }
         if (rc == DF_OK && best >= 0) set_tuned_variant(prec, s.n_nu, best);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -786,7 +815,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
 
 int df_ladder_variant(int32_t n_nu, int32_t prec, char *name, size_t name_len) {
     if (!name || name_len == 0) return DF_E_INVAL;
-    if (prec != DF_FP64 && prec != DF_FP32_REFINE) return DF_E_INVAL;
+    if (!ladder_prec(prec)) return DF_E_INVAL;
     if (n_nu < 2 || (n_nu & 1) || n_nu > 128) return DF_E_UNSUPPORTED;
     const char *v = variant_name(ladder_variant(n_nu, prec));
     if (strlen(v) + 1 > name_len) return DF_E_INVAL;
@@ -795,7 +824,7 @@ int df_ladder_variant(int32_t n_nu, int32_t prec, char *name, size_t name_len) {
 }
 
 int df_ladder_set_variant(int32_t n_nu, int32_t prec, const char *name) {
-    if (prec != DF_FP64 && prec != DF_FP32_REFINE) return DF_E_INVAL;
+    if (!ladder_prec(prec)) return DF_E_INVAL;
     if (n_nu < 2 || (n_nu & 1) || n_nu > 128) return DF_E_UNSUPPORTED;
     const int v = variant_from_name(name);
     if (v < 0) return DF_E_INVAL;

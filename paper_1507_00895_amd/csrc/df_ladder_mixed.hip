@@ -19,6 +19,8 @@
 //   (relative accuracy of |det| about kappa * n * eps32); items near the
 //   instability fail the certificate and take the FP64 path, whose
 //   determinant is exact to FP64 rounding.
+#include <type_traits>
+
 #include "df_gj_core.hpp"
 
 namespace df {
@@ -35,13 +37,20 @@ template <int NP> struct MixedShared {
         } ref;                           // during the refinement
     };
 };
+// Without refinement only the sweep's state is needed.
+template <int NP> struct PlainShared {
+    GjShared<float, NP> gj;
+};
 
-template <int NP>
+// REFINE = false: the FP32 ladder alone, Gamma_nn = sum_l X_nl gamma_ln with
+// X = D^-1 from the FP32 sweep (products and sums in FP64).  Relative error of
+// order kappa eps32, about 1e-6 for certified items.
+template <int NP, bool REFINE>
 __device__ __forceinline__ void mixed_body(LadderArgs a0) {
     constexpr int NT = NP / 16;
     typedef MT<float>::v4 f4;
     typedef MT<double>::v4 d4;
-    __shared__ MixedShared<NP> sh;
+    __shared__ typename std::conditional<REFINE, MixedShared<NP>, PlainShared<NP>>::type sh;
     __shared__ cd ypart[NT][NP];
     __shared__ cd tv[NP];
     __shared__ int s_flag;
@@ -121,6 +130,52 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
     __syncthreads();   // also ends every use of sh.gj
     const int stt = s_flag;
 
+    if constexpr (!REFINE) {
+        if (stt == 0) {
+            // ---- Gamma_nn = sum_l X_nl gamma_ln  (gamma^T read row-wise)
+            const double *gtr = a.gtr + 2 * (size_t)cm * nn;
+            cd yp[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                yp[r] = {0.0, 0.0};
+                const int i = 16 * w + MT<float>::row(lg, r);
+                if (i < n_nu) {
+#pragma unroll
+                    for (int tc = 0; tc < NT; ++tc) {
+                        const int j = 16 * tc + lj;
+                        if (j < n_nu)
+                            yp[r] = fma_c(yp[r], cd{(double)Cr[tc][r], (double)Ci[tc][r]},
+                                          ld(gtr, (size_t)i * n_nu + j));
+                    }
+                }
+            }
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    yp[r].re += __shfl_xor(yp[r].re, off, 64);
+                    yp[r].im += __shfl_xor(yp[r].im, off, 64);
+                }
+            }
+            if (lj == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ypart[0][16 * w + MT<float>::row(lg, r)] = yp[r];
+            }
+        }
+        __syncthreads();
+        for (int n = tid; n < n_nu; n += NP * 4) {
+            const cd tt = tv[n];
+            cd wv;
+            if (stt == 0) {
+                const cd y = ypart[0][n];
+                wv = {y.re - 0.5 * tt.re, y.im - 0.5 * tt.im};
+            } else {
+                const cd gnn = ld(gam, (size_t)n * n_nu + n);
+                wv = {gnn.re + 0.5 * tt.re, gnn.im + 0.5 * tt.im};
+            }
+            st(a.w, ((size_t)cm * n_nu + n) * N + q, wv);
+        }
+    } else {
     if (stt == 0) {
         // ---- share X (all waves' block-rows)
 #pragma unroll
@@ -232,16 +287,26 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
         }
         st(a.w, ((size_t)cm * n_nu + n) * N + q, wv);
     }
+    }   // REFINE
 }
 
 template <int NP>
 __global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a0) {
-    mixed_body<NP>(a0);
+    mixed_body<NP, true>(a0);
 }
 template <int NP>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(3, 3)))
 void k_ladder_mixed_o3(LadderArgs a0) {
-    mixed_body<NP>(a0);
+    mixed_body<NP, true>(a0);
+}
+template <int NP>
+__global__ __launch_bounds__(NP * 4) void k_ladder_fp32(LadderArgs a0) {
+    mixed_body<NP, false>(a0);
+}
+template <int NP>
+__global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_ladder_fp32_o4(LadderArgs a0) {
+    mixed_body<NP, false>(a0);
 }
 
 template <int NP>
@@ -253,6 +318,15 @@ static hipError_t launch_mixed(const LadderArgs &a, int occ, hipStream_t s) {
         }
     }
     hipLaunchKernelGGL((k_ladder_mixed<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NP>
+static hipError_t launch_fp32(const LadderArgs &a, int occ, hipStream_t s) {
+    if (occ == 4)
+        hipLaunchKernelGGL((k_ladder_fp32_o4<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_ladder_fp32<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
     return hipGetLastError();
 }
 
@@ -278,6 +352,20 @@ hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, hipStream_t s) {
         case 32: return launch_mixed<32>(a, occ, s);
         case 48: return launch_mixed<48>(a, occ, s);
         case 64: return launch_mixed<64>(a, 0, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace df
+
+namespace df {
+
+hipError_t launch_ladder_fp32(const LadderArgs &a, int occ, hipStream_t s) {
+    switch (ladder_mixed_padded_size(a.n_nu)) {
+        case 16: return launch_fp32<16>(a, occ, s);
+        case 32: return launch_fp32<32>(a, occ, s);
+        case 48: return launch_fp32<48>(a, occ, s);
+        case 64: return launch_fp32<64>(a, occ, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -15,7 +15,8 @@ namespace df {
 
 namespace {
 
-const char *const kNames[LV_COUNT] = {"gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3"};
+const char *const kNames[LV_COUNT] = {"gjb",   "gjb_o3",   "vector", "mfma",
+                                     "mixed", "mixed_o3", "fp32",   "fp32_o4"};
 
 std::mutex g_mu;
 std::map<std::pair<int, int>, int> g_table;
@@ -62,18 +63,30 @@ int variant_padded_size(int v, int n_nu) {
         case LV_MFMA: return ladder_mfma_padded_size(n_nu);
         case LV_MIXED: return ladder_mixed_padded_size(n_nu);
         case LV_MIXED_O3: return ladder_mixed_has_occ3(n_nu) ? ladder_mixed_padded_size(n_nu) : 0;
+        case LV_FP32:
+        case LV_FP32_O4: return ladder_mixed_padded_size(n_nu);
         default: return 0;
     }
 }
 
-bool variant_supports(int v, int n_nu, int prec) {
-    const bool mixed = (v == LV_MIXED || v == LV_MIXED_O3);
-    if (mixed != (prec == DF_FP32_REFINE)) {
-        // the FP64 kernels also serve FP32_REFINE requests beyond the mixed
-        // kernels' size limit
-        if (!(prec == DF_FP32_REFINE && !mixed && ladder_mixed_padded_size(n_nu) == 0)) return false;
+int variant_prec(int v) {
+    switch (v) {
+        case LV_MIXED:
+        case LV_MIXED_O3: return DF_FP32_REFINE;
+        case LV_FP32:
+        case LV_FP32_O4: return DF_FP32;
+        default: return DF_FP64;
     }
-    return variant_padded_size(v, n_nu) != 0;
+}
+
+// A request is served by the variants of its own precision class; where that
+// class has no kernel for n_nu (the FP32 kernels stop at n_nu = 64), by the
+// FP64 variants.
+bool variant_supports(int v, int n_nu, int prec) {
+    if (variant_padded_size(v, n_nu) == 0) return false;
+    const int vp = variant_prec(v);
+    if (vp == prec) return true;
+    return vp == DF_FP64 && prec != DF_FP64 && ladder_mixed_padded_size(n_nu) == 0;
 }
 
 int tuned_variant(int prec, int n_nu) {

@@ -16,12 +16,15 @@ enum LadderVariant {
     LV_MFMA = 3,       // partial pivoting, FP64 MFMA trailing updates
     LV_MIXED = 4,      // certified FP32 sweep + FP64 residual correction
     LV_MIXED_O3 = 5,   // same, capped for three waves per SIMD
-    LV_COUNT = 6
+    LV_FP32 = 6,       // certified FP32 sweep alone
+    LV_FP32_O4 = 7,    // same, capped for four waves per SIMD
+    LV_COUNT = 8
 };
 
 const char *variant_name(int v);
 int variant_from_name(const char *name);          // -1 if unknown
-bool variant_supports(int v, int n_nu, int prec);   // kernel exists for this n_nu and precision
+int variant_prec(int v);                            // precision class the variant delivers
+bool variant_supports(int v, int n_nu, int prec);   // serves requests of this n_nu and precision
 int variant_padded_size(int v, int n_nu);
 
 // tuned choice for (prec, n_nu), or -1

@@ -48,9 +48,10 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "df.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(df_inst_t), offsetof(df_inst_t, beta),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(df_inst_t), offsetof(df_inst_t, beta),
          offsetof(df_inst_t, g), offsetof(df_inst_t, status), sizeof(df_opts_t),
-         offsetof(df_opts_t, max_iter));
+         offsetof(df_opts_t, max_iter), offsetof(df_opts_t, tol), offsetof(df_opts_t, switch_tol),
+         offsetof(df_opts_t, reserved));
   return 0;
 }
 ''')
@@ -59,7 +60,8 @@ int main(void) {
     vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     assert vals == [ctypes.sizeof(B.DfInst), B.DfInst.beta.offset, B.DfInst.g.offset,
-                    B.DfInst.status.offset, ctypes.sizeof(B.DfOpts), B.DfOpts.max_iter.offset]
+                    B.DfInst.status.offset, ctypes.sizeof(B.DfOpts), B.DfOpts.max_iter.offset,
+                    B.DfOpts.tol.offset, B.DfOpts.switch_tol.offset, B.DfOpts.reserved.offset]
 
 
 def _inst(**kw):
@@ -101,6 +103,13 @@ def test_workspace_size_and_validation_order():
     bad = B.make_opts(mix=0.0)
     assert lib.df_iterate(arr, 1, ctypes.byref(bad), None, None, 0x1000, n.value, None) == B.DF_E_INVAL
     bad = B.make_opts(prec=7)
+    assert lib.df_ladder_solve(arr, 1, ctypes.byref(bad), 0x1000, n.value, None) == B.DF_E_INVAL
+    # the adaptive schedule belongs to the loop only
+    ad = B.make_opts(prec=B.DF_ADAPTIVE)
+    assert lib.df_ladder_solve(arr, 1, ctypes.byref(ad), 0x1000, n.value, None) == B.DF_E_INVAL
+    assert lib.df_workspace_size(arr, 1, ctypes.byref(ad), ctypes.byref(n)) == B.DF_OK
+    bad = B.make_opts()
+    bad.reserved = 1
     assert lib.df_ladder_solve(arr, 1, ctypes.byref(bad), 0x1000, n.value, None) == B.DF_E_INVAL
     assert B.df_strerror(B.DF_E_WORKSPACE).startswith("workspace")
     assert B.df_version() >= 100
@@ -145,11 +154,16 @@ def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     assert B.df_ladder_variant(64, B.DF_FP32_REFINE) == "mixed"
     assert B.df_ladder_variant(96, B.DF_FP32_REFINE) == "gjb"      # beyond the mixed kernel
     assert B.df_ladder_variant(128, B.DF_FP64) == "vector"
+    assert B.df_ladder_variant(64, B.DF_FP32) == "fp32"
+    assert B.df_ladder_variant(128, B.DF_FP32) == "vector"
+    with pytest.raises(B.DfError):
+        B.df_ladder_variant(64, B.DF_ADAPTIVE)
     B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o3")
     assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3"
     assert B.df_ladder_variant(62, B.DF_FP64) == "gjb"               # keyed by exact n_nu
     for bad in [(96, B.DF_FP64, "gjb_o3"), (128, B.DF_FP64, "gjb"), (64, B.DF_FP64, "mixed"),
-                (64, B.DF_FP32_REFINE, "vector"), (64, B.DF_FP32_REFINE, "mixed_o3")]:
+                (64, B.DF_FP32_REFINE, "vector"), (64, B.DF_FP32_REFINE, "mixed_o3"),
+                (64, B.DF_FP32, "mixed"), (64, B.DF_FP64, "fp32_o4"), (96, B.DF_FP32, "fp32")]:
         with pytest.raises(B.DfError) as e:
             B.df_ladder_set_variant(*bad)
         assert e.value.code == B.DF_E_UNSUPPORTED

@@ -57,7 +57,7 @@ def test_mixed_ladder_parity(B, shape):
     ws = B.workspace([inst])
     B.df_dual_gf([inst], ws)
     B.df_bubble([inst], ws)
-    B.df_ladder_solve([inst], ws, B.make_opts(prec=B.DF_FP32_REFINE, max_refine=1))
+    B.df_ladder_solve([inst], ws, B.make_opts(prec=B.DF_FP32_REFINE))
     torch.cuda.synchronize()
     chi = host(inst.chi)
     gam = O.spin_channels(p.gamma_uu, p.gamma_ud)
@@ -119,3 +119,68 @@ def test_mixed_converges_to_fp64_fixed_point(B):
         torch.cuda.synchronize()
         out[prec] = host(inst.sigma)
     assert rel(out[B.DF_FP32_REFINE], out[B.DF_FP64]) <= TOL_MIXED
+
+
+# ---------------------------------------------------------------- FP32 ladders and the adaptive loop
+# A certified FP32 ladder (rho(|M|) < 0.99, so kappa <= 100 after diagonal
+# scaling) carries a relative error of about kappa * n * eps32 in the worst
+# case; 2e-5 is the bound stated for W.
+TOL_FP32 = 2e-5
+
+
+@pytest.mark.parametrize("shape", SHAPES[:6], ids=["D{}nk{}nu{}om{}".format(*s[:4]) for s in SHAPES[:6]])
+def test_fp32_ladder_parity(B, shape):
+    import torch
+    p = I.atomic_limit_problem(*shape)
+    inst = B.make_instance(p)
+    ws = B.workspace([inst])
+    B.df_dual_gf([inst], ws)
+    B.df_bubble([inst], ws)
+    B.df_ladder_solve([inst], ws, B.make_opts(prec=B.DF_FP32))
+    torch.cuda.synchronize()
+    chi = host(inst.chi)
+    N = p.N
+    qs = np.arange(N) if N * p.n_nu ** 3 * p.n_om <= 3e8 else \
+        np.unique(np.concatenate([[0, N - 1], np.random.default_rng(1).choice(N, 30, replace=False)]))
+    lr = O.ladder(O.spin_channels(p.gamma_uu, p.gamma_ud), chi[:, :, qs])
+    assert np.array_equal(host(inst.status)[:, :, qs], lr.status)
+    assert rel(host(inst.w)[..., qs], lr.W) <= TOL_FP32
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_adaptive_converges_to_fp64_fixed_point(B, use_graph):
+    """FP32 ladders until the diff drops below switch_tol, FP64 after: the
+    converged Sigma~ is the FP64 path's (both to tol 1e-11)."""
+    import torch
+    probs = [I.atomic_limit_problem(2, 16, 32, 7, 20.0, 1.0, 0.1),
+             I.atomic_limit_problem(2, 8, 64, 5, 10.0, 3.0, 0.1)]
+    out = {}
+    for prec in (B.DF_FP64, B.DF_ADAPTIVE):
+        insts = [B.make_instance(p) for p in probs]
+        ws = B.workspace(insts)
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        code, iters, d = B.df_iterate(insts, ws, B.make_opts(prec=prec, mix=0.5, tol=1e-11,
+                                                             max_iter=300, use_graph=use_graph,
+                                                             switch_tol=1e-5),
+                                      stream=s.cuda_stream)
+        s.synchronize()
+        assert max(d) < 1e-11
+        out[prec] = [host(x.sigma) for x in insts]
+    for a, b in zip(out[B.DF_ADAPTIVE], out[B.DF_FP64]):
+        assert rel(a, b) <= TOL_MIXED
+
+
+def test_adaptive_never_converges_in_fp32(B):
+    """A switch threshold below tol must not let an instance stop on FP32 ladders."""
+    import torch
+    p = I.workload_small()[0]
+    res = {}
+    for prec, sw in ((B.DF_FP64, 0.0), (B.DF_ADAPTIVE, 1e-12)):
+        inst = B.make_instance(p)
+        ws = B.workspace([inst])
+        B.df_iterate([inst], ws, B.make_opts(prec=prec, mix=0.5, tol=1e-9, max_iter=300,
+                                             switch_tol=sw))
+        torch.cuda.synchronize()
+        res[prec] = host(inst.sigma)
+    assert rel(res[B.DF_ADAPTIVE], res[B.DF_FP64]) <= 1e-8

@@ -10,7 +10,7 @@ from paper_1507_00895_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-12, 1: 1e-9}
+TOL = {0: 1e-12, 1: 1e-9, 2: 2e-5}
 
 
 def rel(x, ref):
@@ -49,7 +49,7 @@ def _ladder_case(B, shape, prec):
 def test_every_variant_matches_oracle(B, shape):
     import torch
     n_nu = shape[2]
-    for prec in (B.DF_FP64, B.DF_FP32_REFINE):
+    for prec in (B.DF_FP64, B.DF_FP32_REFINE, B.DF_FP32):
         p, inst, ws = _ladder_case(B, shape, prec)
         chi = inst.chi.cpu().numpy()
         lr = O.ladder(O.spin_channels(p.gamma_uu, p.gamma_ud), chi)
