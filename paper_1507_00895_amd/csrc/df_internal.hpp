@@ -106,6 +106,17 @@ __device__ __forceinline__ int resolve_item(LadderArgs &a, int item) {
     return item - d.item0;
 }
 
+// Work-group b of a launch runs on XCD b % 8 (the dispatcher deals work-groups
+// round-robin over the eight XCDs, each with its own L2).  Give every XCD one
+// contiguous range of the n items instead, so that the neighbouring q of one
+// (channel, Om) - which share the cache lines of chi and W - meet in one L2.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+    constexpr int kXcd = 8;
+    const int per = n / kXcd, rem = n % kXcd;
+    const int x = b % kXcd, i = b / kXcd;
+    return x * per + (x < rem ? x : rem) + i;
+}
+
 hipError_t launch_dual_gf(const DualGfArgs &a, hipStream_t s);
 hipError_t launch_bubble(const BubbleArgs &a, hipStream_t s);
 hipError_t launch_sigma_part(const SigmaArgs &a, hipStream_t s);

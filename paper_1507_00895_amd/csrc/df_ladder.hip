@@ -57,7 +57,8 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a0) {
     for (int wi = a0.in_queue ? (int)blockIdx.x : 0; wi < n_work;
          wi += (a0.in_queue ? (int)gridDim.x : 1)) {
     LadderArgs a = a0;
-    const int item = resolve_item(a, a0.in_queue ? a0.in_queue[wi] : a0.item0 + blockIdx.x);
+    const int item = resolve_item(a, a0.in_queue ? a0.in_queue[wi]
+                                                  : a0.item0 + xcd_item(blockIdx.x, gridDim.x));
     const int n_nu = a.n_nu, N = a.N;
     const int q = item % N;
     const int cm = item / N;                 // c * n_om + m

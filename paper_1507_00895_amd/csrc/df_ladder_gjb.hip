@@ -30,7 +30,7 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
     const int lj = l & 15;
     const int lg = l >> 4;
     LadderArgs a = a0;
-    const int gitem = a0.item0 + blockIdx.x;            // global item (fused launches)
+    const int gitem = a0.item0 + xcd_item(blockIdx.x, gridDim.x);   // global item (fused launches)
     const int item = resolve_item(a, gitem);
     const int n_nu = a.n_nu, N = a.N;
     const int q = item % N;

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(NP * 4) void k_ladder_mfma_f64(LadderArgs a0) {
     const int lj = l & 15;           // column inside a tile
     const int lg = l >> 4;           // row group: rows lg + 4 r, r = 0..3
     LadderArgs a = a0;
-    const int gitem = a0.item0 + blockIdx.x;            // global item (fused launches)
+    const int gitem = a0.item0 + xcd_item(blockIdx.x, gridDim.x);   // global item (fused launches)
     const int item = resolve_item(a, gitem);
     const int n_nu = a.n_nu, N = a.N;
     const int q = item % N;
