@@ -63,11 +63,16 @@ template <typename T> __device__ __forceinline__ cplx<T> cdiv(cplx<T> a, cplx<T>
 }
 template <typename T> __device__ __forceinline__ T cabs1(cplx<T> a) { return fabs(a.re) + fabs(a.im); }
 
+// Every array these kernels read or write through ld/st lives in device
+// global memory: say so, so that the compiler emits global (not flat) loads
+// and stores, which do not share a wait counter with LDS traffic.
+typedef double dv2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ cd ld(const double *p, size_t i) {
-    return *reinterpret_cast<const cd *>(p + 2 * i);
+    const dv2 v = *(__attribute__((address_space(1))) const dv2 *)(const void *)(p + 2 * i);
+    return {v.x, v.y};
 }
 __device__ __forceinline__ void st(double *p, size_t i, cd v) {
-    *reinterpret_cast<cd *>(p + 2 * i) = v;
+    *(__attribute__((address_space(1))) dv2 *)(void *)(p + 2 * i) = dv2{v.re, v.im};
 }
 
 // ----------------------------------------------------------------- k-grid

@@ -12,13 +12,14 @@
 // H-matrix: its leading blocks are nonsingular and elimination without
 // pivoting is stable.  gj_certify bounds rho(|M|) from above by the
 // Collatz-Wielandt quotient max_i (B v)_i / v_i after power steps on
-// B = cabs1(M) + eps I (cabs1 = |re| + |im| >= |.|).  The bound also limits the
+// B = cabs1(M) + eps I (cabs1 = |re| + |im| >= |.|), stopping at the first
+// step whose bound already passes.  The bound also limits the
 // condition number of D after diagonal scaling: ||D'^-1|| <= 1 / (1 - rho).
 //
 // Sweep.  For each tile column t: wave t inverts the diagonal tile A_tt by 16
-// scalar Gauss-Jordan steps held in registers (pivot by readlane, pivot-column
-// values within a quad by DPP, pivot-row values by bpermute) and publishes it
-// with its old block-row; every other wave forms G_w = -A_wt A_tt^-1; every
+// scalar Gauss-Jordan steps on its accumulator registers (pivot by readlane,
+// pivot-column values within a 16-lane row by DPP, the pivot-row value of a
+// lane's column by bpermute) and publishes it with its old block-row; every other wave forms G_w = -A_wt A_tt^-1; every
 // wave applies A_w,c += G_w A_t,c (c != t) with G_t = A_tt^-1 - 1 and sets
 // tile (w, t) to G_w (A_tt^-1 for w = t).  This is the block form of the
 // in-place sweep: afterwards the tiles hold D^-1, and the scalar pivots
@@ -38,6 +39,9 @@ template <> struct MT<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int lg, int r) { return lg + 4 * r; }
+    // row s of a tile sits in row group lg_of(s), register r_of(s)
+    static __device__ __forceinline__ int lg_of(int s) { return s & 3; }
+    static __device__ __forceinline__ int r_of(int s) { return s >> 2; }
 };
 template <> struct MT<float> {
     typedef float v4 __attribute__((ext_vector_type(4)));
@@ -45,6 +49,8 @@ template <> struct MT<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int lg, int r) { return 4 * lg + r; }
+    static __device__ __forceinline__ int lg_of(int s) { return s >> 2; }
+    static __device__ __forceinline__ int r_of(int s) { return s & 3; }
 };
 
 // ---------------------------------------------------------------- lane ops
@@ -78,6 +84,41 @@ __device__ __forceinline__ double quad_bcast_v(double v, int k) {
 }
 __device__ __forceinline__ float quad_bcast_v(float v, int k) {
     return __int_as_float(quad_bcast_rt(__float_as_int(v), k));
+}
+
+// value of lane n of the caller's own 16-lane row (DPP row_newbcast; n resolves
+// statically once the caller's loop unrolls)
+template <int N> __device__ __forceinline__ int row_bcast_i(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int row_bcast_rt(int v, int n) {
+    switch (n) {
+        case 0: return row_bcast_i<0>(v);
+        case 1: return row_bcast_i<1>(v);
+        case 2: return row_bcast_i<2>(v);
+        case 3: return row_bcast_i<3>(v);
+        case 4: return row_bcast_i<4>(v);
+        case 5: return row_bcast_i<5>(v);
+        case 6: return row_bcast_i<6>(v);
+        case 7: return row_bcast_i<7>(v);
+        case 8: return row_bcast_i<8>(v);
+        case 9: return row_bcast_i<9>(v);
+        case 10: return row_bcast_i<10>(v);
+        case 11: return row_bcast_i<11>(v);
+        case 12: return row_bcast_i<12>(v);
+        case 13: return row_bcast_i<13>(v);
+        case 14: return row_bcast_i<14>(v);
+        default: return row_bcast_i<15>(v);
+    }
+}
+__device__ __forceinline__ double row_bcast_v(double v, int n) {
+    const long long b = __double_as_longlong(v);
+    const int lo = row_bcast_rt((int)(b & 0xffffffffLL), n);
+    const int hi = row_bcast_rt((int)(b >> 32), n);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float row_bcast_v(float v, int n) {
+    return __int_as_float(row_bcast_rt(__float_as_int(v), n));
 }
 
 // value held by the lane at byte address addr (= 4 * lane)
@@ -131,57 +172,98 @@ template <typename T, int NP> struct GjShared {
     cplx<T> Xw[NT][16][17];      // per-wave layout exchange (accumulator -> operand)
     cd pivv[NP];                 // scalar pivots, FP64
     double vbuf[2][NP];          // power-iteration vectors
-    double wmax[NT];
+    double wmax[2][NT];          // double-buffered: a wave may start the next step early
 };
 
-// Collatz-Wielandt bound of rho(cabs1(M) + eps I) for M = 1 - D; uniform
-// result across the work-group.  Contains barriers: every thread must call.
+// Sum over the 16 lanes of the caller's DPP row, returned to all of them
+// (pairs by quad_perm, then rotations by 4 and 8 within the row).
+template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL,
+                                                      0xf, 0xf, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float row16_sum(float x) {
+    x += dpp_f<0xB1>(x);    // quad_perm [1,0,3,2]
+    x += dpp_f<0x4E>(x);    // quad_perm [2,3,0,1]
+    x += dpp_f<0x124>(x);   // row_ror:4
+    x += dpp_f<0x128>(x);   // row_ror:8
+    return x;
+}
+__device__ __forceinline__ double row16_sum(double x) {
+    x += dpp_d<0xB1>(x);
+    x += dpp_d<0x4E>(x);
+    x += dpp_d<0x124>(x);
+    x += dpp_d<0x128>(x);
+    return x;
+}
+__device__ __forceinline__ cd row16_sum(cd x) { return {row16_sum(x.re), row16_sum(x.im)}; }
+
+// Collatz-Wielandt bound of rho(cabs1(M) + eps I), eps = 1e-6 (it keeps every
+// component of v positive and normal in FP32 over the steps taken, and
+// raises the bound by eps at most), for M = 1 - D; uniform result across the
+// work-group.  Power steps from v = 1; after each step from
+// the second on, the bound max_i (B v)_i / v_i is formed and the loop stops
+// as soon as it is below `accept` (any positive v gives a valid bound).  The
+// arithmetic is FP32: every term is non-negative, so the computed sums are
+// within n * 2^-24 relative of the exact ones, and the bound is inflated by
+// (1 + 1e-5) to stay an upper bound.  Contains barriers: every thread must call.
 template <typename T, int NP>
 __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP / 16],
                                              const typename MT<T>::v4 (&Ci)[NP / 16],
-                                             GjShared<T, NP> &sh, int iters) {
+                                             GjShared<T, NP> &sh, int iters, double accept) {
     constexpr int NT = NP / 16;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
     for (int i = tid; i < NP; i += NP * 4) sh.vbuf[0][i] = 1.0;
     __syncthreads();
+    double cw = INFINITY;
     for (int it = 0; it < iters; ++it) {
         const double *v = sh.vbuf[it & 1];
-        double u[4] = {0.0, 0.0, 0.0, 0.0};
+        float u[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int tc = 0; tc < NT; ++tc) {
             const int j = 16 * tc + lj;
-            const double vj = v[j];
+            const float vj = (float)v[j];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 16 * w + MT<T>::row(lg, r);
-                const double mr = ((i == j) ? 1.0 : 0.0) - (double)Cr[tc][r];
-                const double b = fabs(mr) + fabs((double)Ci[tc][r]) + ((i == j) ? 1e-12 : 0.0);
-                u[r] = fma(b, vj, u[r]);
+                const float mr = (float)(((i == j) ? T(1) : T(0)) - Cr[tc][r]);
+                const float b = fabsf(mr) + fabsf((float)Ci[tc][r]) + ((i == j) ? 1e-6f : 0.0f);
+                u[r] = fmaf(b, vj, u[r]);
             }
         }
-        // rows live in the 16 lanes of one row group (FP64) or one quarter (FP32)
+        // rows live in the 16 lanes of one DPP row (FP64 layout) or of one
+        // quarter (FP32 layout): either way one row of 16 lanes
 #pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) u[r] += __shfl_xor(u[r], off, 64);
-        }
-        if (it == iters - 1) {
-            double ratio = 0.0;
+        for (int r = 0; r < 4; ++r) u[r] = row16_sum(u[r]);
+        const bool bound = (it >= 1);
+        if (bound) {
+            float ratio = 0.f;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double rr = u[r] / v[16 * w + MT<T>::row(lg, r)];
+                const float rr = u[r] * __builtin_amdgcn_rcpf((float)v[16 * w + MT<T>::row(lg, r)]);
                 ratio = rr > ratio ? rr : ratio;
             }
-            const double m = wave_max_pos(ratio);
-            if (l == 0) sh.wmax[w] = m;
-        } else if (lj == 0) {
+            const double m = wave_max_pos((double)ratio);
+            if (l == 0) sh.wmax[it & 1][w] = m;
+        }
+        if (lj == 0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) sh.vbuf[(it + 1) & 1][16 * w + MT<T>::row(lg, r)] = u[r];
         }
         __syncthreads();
+        if (bound) {
+            double c = 0.0;
+            for (int x = 0; x < NT; ++x) c = sh.wmax[it & 1][x] > c ? sh.wmax[it & 1][x] : c;
+            // rcpf is within 1 ulp; the factor covers it and the sums' rounding
+            cw = c * (1.0 + 1e-5);
+            if (cw < accept) break;   // uniform: every thread read the same wmax
+        }
     }
-    double cw = 0.0;
-    for (int x = 0; x < NT; ++x) cw = sh.wmax[x] > cw ? sh.wmax[x] : cw;
     return cw;
 }
 
@@ -198,42 +280,44 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
         if (w == t) {
 #pragma unroll
             for (int tc = 0; tc < NT; ++tc) {
+                if (tc == t) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const ct v = {Cr[tc][r], Ci[tc][r]};
-                    const int i = MT<T>::row(lg, r);
-                    if (tc == t) sh.Tt[i][lj] = v;
-                    else sh.Rb[i][16 * tc + lj] = v;
-                }
+                for (int r = 0; r < 4; ++r)
+                    sh.Rb[MT<T>::row(lg, r)][16 * tc + lj] = ct{Cr[tc][r], Ci[tc][r]};
             }
-            wave_sync_lds();
-            // 16 scalar steps: lane holds row l/4, columns 4 (l % 4) + e
-            const int gi = l >> 2;
-            const int gq = (l & 3) * 4;
-            ct x[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) x[e] = sh.Tt[gi][gq + e];
+            // Invert A_tt in place, in the accumulator layout (lane: column lj,
+            // rows MT<T>::row(lg, r)), by 16 scalar steps: pivot by readlane,
+            // pivot column within the lane's 16-lane row by DPP row_newbcast,
+            // pivot-row value of the lane's column by one bpermute.
+            v4 &Xr = Cr[t];
+            v4 &Xi = Ci[t];
+            cd pvl = {0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
-                const int src = 4 * s + (s >> 2);
-                const ct piv = {readlane_v(x[s & 3].re, src), readlane_v(x[s & 3].im, src)};
+                const int ls = MT<T>::lg_of(s), rs = MT<T>::r_of(s);
+                const int src = s + 16 * ls;
+                const ct piv = {readlane_v(Xr[rs], src), readlane_v(Xi[rs], src)};
+                const int from = (lj + 16 * ls) << 2;
+                const ct rr = {bperm_v(from, Xr[rs]), bperm_v(from, Xi[rs])};
+                ct c[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) c[r] = {row_bcast_v(Xr[r], s), row_bcast_v(Xi[r], s)};
                 const ct ip = recip_fast(piv);
-                const ct cvl = {quad_bcast_v(x[s & 3].re, s >> 2), quad_bcast_v(x[s & 3].im, s >> 2)};
-                const int from = (4 * s + (l & 3)) << 2;
-                ct rr[4];
+                const bool colj = (lj == s);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) rr[e] = {bperm_v(from, x[e].re), bperm_v(from, x[e].im)};
-                const bool me = (gi == s);
-                const ct f = me ? ct{T(1) - ip.re, -ip.im} : cvl * ip;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    x[e] = fms(x[e], f, rr[e]);
-                    if (gq + e == s) x[e] = me ? ip : ct{-f.re, -f.im};
+                for (int r = 0; r < 4; ++r) {
+                    const bool me = (r == rs) && (lg == ls);
+                    const ct f = me ? ct{T(1) - ip.re, -ip.im} : c[r] * ip;
+                    ct x = fms(ct{Xr[r], Xi[r]}, f, rr);
+                    if (colj) x = me ? ip : ct{-f.re, -f.im};
+                    Xr[r] = x.re;
+                    Xi[r] = x.im;
                 }
-                if (l == 0) sh.pivv[16 * t + s] = cd{(double)piv.re, (double)piv.im};
+                if (l == s) pvl = cd{(double)piv.re, (double)piv.im};
             }
+            if (l < 16) sh.pivv[16 * t + l] = pvl;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) sh.Tt[gi][gq + e] = x[e];
+            for (int r = 0; r < 4; ++r) sh.Tt[MT<T>::row(lg, r)][lj] = ct{Xr[r], Xi[r]};
         } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Cr[t][r], Ci[t][r]};
@@ -249,12 +333,6 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
                 gr[k4] = g.re;
                 gim[k4] = g.im;
                 gn[k4] = -g.im;
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const ct v = sh.Tt[MT<T>::row(lg, r)][lj];
-                Cr[t][r] = v.re;
-                Ci[t][r] = v.im;
             }
         } else {
             v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};

@@ -41,43 +41,44 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
     const double *pm = a.pdm + 2 * (size_t)cm * nn;
     const double *gtr = a.gtr + 2 * (size_t)cm * nn;
 
-    // ---- D = 1 - gamma diag(chi) in accumulator tiles, t_i = (gamma chi gamma)_ii
+    // ---- D = 1 - gamma diag(chi) in accumulator tiles, t_i = (gamma chi gamma)_ii.
+    // Per tile column, all loads first and without branches (indices clamped
+    // into the matrix, the padding masked afterwards), so that they are in
+    // flight together.
     d4 Cr[NT], Ci[NT];
     cd tp[4];
+    const int nm1 = n_nu - 1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) {
         const int j = 16 * tc + lj;
-        const cd xj = (j < n_nu) ? ld(a.chi, ((size_t)im * n_nu + j) * N + q) : cd{0.0, 0.0};
+        const cd xj = ld(a.chi, ((size_t)im * n_nu + min(j, nm1)) * N + q);
+        cd gv[4], pv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const size_t e = (size_t)min(16 * w + MT<double>::row(lg, r), nm1) * n_nu + min(j, nm1);
+            gv[r] = ld(gam, e);
+            pv[r] = ld(pm, e);
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = 16 * w + MT<double>::row(lg, r);
-            double dr = (i == j) ? 1.0 : 0.0, di = 0.0;
-            if (i < n_nu && j < n_nu) {
-                const cd x = ld(gam, (size_t)i * n_nu + j) * xj;
-                dr -= x.re;
-                di = -x.im;
-                tp[r] = fma_c(tp[r], ld(pm, (size_t)i * n_nu + j), xj);
-            }
-            Cr[tc][r] = dr;
-            Ci[tc][r] = di;
+            const bool in = (i < n_nu) && (j < n_nu);
+            const cd x = gv[r] * xj;
+            Cr[tc][r] = (((i == j) ? 1.0 : 0.0) - (in ? x.re : 0.0));
+            Ci[tc][r] = (in ? -x.im : 0.0);
+            tp[r] = fma_c(tp[r], in ? pv[r] : cd{0.0, 0.0}, xj);
         }
     }
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            tp[r].re += __shfl_xor(tp[r].re, off, 64);
-            tp[r].im += __shfl_xor(tp[r].im, off, 64);
-        }
-    }
+    for (int r = 0; r < 4; ++r) tp[r] = row16_sum(tp[r]);
     if (lj == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) tv[16 * w + MT<double>::row(lg, r)] = tp[r];
     }
 
-    const double cw = gj_certify<double, NP>(Cr, Ci, sh, CERT_ITERS);
+    const double cw = gj_certify<double, NP>(Cr, Ci, sh, CERT_ITERS, CERT_MAX_F64);
     if (!(cw < CERT_MAX_F64)) {
         if (tid == 0 && a.queue) a.queue[atomicAdd(a.queue_count, 1)] = gitem;
         return;   // uniform: every thread of the work-group leaves here
@@ -117,13 +118,7 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
             }
         }
 #pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                yp[r].re += __shfl_xor(yp[r].re, off, 64);
-                yp[r].im += __shfl_xor(yp[r].im, off, 64);
-            }
-        }
+        for (int r = 0; r < 4; ++r) yp[r] = row16_sum(yp[r]);
         if (lj == 0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) yv[16 * w + MT<double>::row(lg, r)] = yp[r];

@@ -72,43 +72,50 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
     const double *pm = a.pdm + 2 * (size_t)cm * nn;
     const double *chi = a.chi + 2 * ((size_t)im * n_nu) * N;   // chi[j] at chi + 2 (j N + q)
 
-    // ---- D in FP32 tiles (FP32 accumulator layout), t_i in FP64
+    // ---- D in FP32 tiles (FP32 accumulator layout), t_i in FP64.  Per tile
+    // column, all loads first and without branches (indices clamped, the
+    // padding masked afterwards).
     f4 Cr[NT], Ci[NT];
     cd tp[4];
+    const int nm1 = n_nu - 1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) {
         const int j = 16 * tc + lj;
-        const cd xj = (j < n_nu) ? ld(chi, (size_t)j * N + q) : cd{0.0, 0.0};
+        const cd xj = ld(chi, (size_t)min(j, nm1) * N + q);
+        // two rows per batch of loads: the FP32 kernels run on a tighter
+        // register budget
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = 16 * w + MT<float>::row(lg, r);
-            double dr = (i == j) ? 1.0 : 0.0, di = 0.0;
-            if (i < n_nu && j < n_nu) {
-                const cd x = ld(gam, (size_t)i * n_nu + j) * xj;
-                dr -= x.re;
-                di = -x.im;
-                tp[r] = fma_c(tp[r], ld(pm, (size_t)i * n_nu + j), xj);
+        for (int r0 = 0; r0 < 4; r0 += 2) {
+            cd gv[2], pv[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const size_t e =
+                    (size_t)min(16 * w + MT<float>::row(lg, r0 + k), nm1) * n_nu + min(j, nm1);
+                gv[k] = ld(gam, e);
+                pv[k] = ld(pm, e);
             }
-            Cr[tc][r] = (float)dr;
-            Ci[tc][r] = (float)di;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int r = r0 + k;
+                const int i = 16 * w + MT<float>::row(lg, r);
+                const bool in = (i < n_nu) && (j < n_nu);
+                const cd x = gv[k] * xj;
+                Cr[tc][r] = (float)(((i == j) ? 1.0 : 0.0) - (in ? x.re : 0.0));
+                Ci[tc][r] = (float)(in ? -x.im : 0.0);
+                tp[r] = fma_c(tp[r], in ? pv[k] : cd{0.0, 0.0}, xj);
+            }
         }
     }
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            tp[r].re += __shfl_xor(tp[r].re, off, 64);
-            tp[r].im += __shfl_xor(tp[r].im, off, 64);
-        }
-    }
+    for (int r = 0; r < 4; ++r) tp[r] = row16_sum(tp[r]);
     if (lj == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) tv[16 * w + MT<float>::row(lg, r)] = tp[r];
     }
 
-    const double cw = gj_certify<float, NP>(Cr, Ci, sh.gj, MIX_CERT_ITERS);
+    const double cw = gj_certify<float, NP>(Cr, Ci, sh.gj, MIX_CERT_ITERS, CERT_MAX_MIXED);
     if (!(cw < CERT_MAX_MIXED)) {
         if (tid == 0 && a.queue) a.queue[atomicAdd(a.queue_count, 1)] = gitem;
         return;   // uniform: every thread of the work-group leaves here
@@ -150,13 +157,7 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
                 }
             }
 #pragma unroll
-            for (int off = 8; off >= 1; off >>= 1) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    yp[r].re += __shfl_xor(yp[r].re, off, 64);
-                    yp[r].im += __shfl_xor(yp[r].im, off, 64);
-                }
-            }
+            for (int r = 0; r < 4; ++r) yp[r] = row16_sum(yp[r]);
             if (lj == 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) ypart[0][16 * w + MT<float>::row(lg, r)] = yp[r];
