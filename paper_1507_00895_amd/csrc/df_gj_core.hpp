@@ -89,7 +89,7 @@ __device__ __forceinline__ float quad_bcast_v(float v, int k) {
 // value of lane n of the caller's own 16-lane row (DPP row_newbcast; n resolves
 // statically once the caller's loop unrolls)
 template <int N> __device__ __forceinline__ int row_bcast_i(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int row_bcast_rt(int v, int n) {
     switch (n) {
@@ -111,11 +111,29 @@ __device__ __forceinline__ int row_bcast_rt(int v, int n) {
         default: return row_bcast_i<15>(v);
     }
 }
-__device__ __forceinline__ double row_bcast_v(double v, int n) {
+template <int N> __device__ __forceinline__ double row_bcast_d(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = row_bcast_rt((int)(b & 0xffffffffLL), n);
-    const int hi = row_bcast_rt((int)(b >> 32), n);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    return __longlong_as_double(__builtin_amdgcn_mov_dpp(b, 0x150 + N, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double row_bcast_v(double v, int n) {
+    switch (n) {   // one 64-bit DPP move (DPP64 supports row_newbcast)
+        case 0: return row_bcast_d<0>(v);
+        case 1: return row_bcast_d<1>(v);
+        case 2: return row_bcast_d<2>(v);
+        case 3: return row_bcast_d<3>(v);
+        case 4: return row_bcast_d<4>(v);
+        case 5: return row_bcast_d<5>(v);
+        case 6: return row_bcast_d<6>(v);
+        case 7: return row_bcast_d<7>(v);
+        case 8: return row_bcast_d<8>(v);
+        case 9: return row_bcast_d<9>(v);
+        case 10: return row_bcast_d<10>(v);
+        case 11: return row_bcast_d<11>(v);
+        case 12: return row_bcast_d<12>(v);
+        case 13: return row_bcast_d<13>(v);
+        case 14: return row_bcast_d<14>(v);
+        default: return row_bcast_d<15>(v);
+    }
 }
 __device__ __forceinline__ float row_bcast_v(float v, int n) {
     return __int_as_float(row_bcast_rt(__float_as_int(v), n));
@@ -143,11 +161,11 @@ __device__ __forceinline__ cd recip_fast(cd z) {
     y = fma(y, e, y);
     return {z.re * y, -z.im * y};
 }
+// (FP32: the hardware reciprocal is within 2 ulp, measured, enough for the
+// FP32 ladder whose own error is of order kappa * n * 2^-24)
 __device__ __forceinline__ cf recip_fast(cf z) {
     const float m = fmaf(z.re, z.re, z.im * z.im);
-    float y = __builtin_amdgcn_rcpf(m);
-    const float e = fmaf(-m, y, 1.0f);
-    y = fmaf(y, e, y);
+    const float y = __builtin_amdgcn_rcpf(m);
     return {z.re * y, -z.im * y};
 }
 
@@ -267,7 +285,55 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
     return cw;
 }
 
+// Invert one 16 x 16 complex tile in place, held by one wave in the MFMA
+// accumulator layout (lane: column lj, rows MT<T>::row(lg, r)), by 16 scalar
+// Gauss-Jordan steps without pivoting: pivot by readlane, pivot column within
+// the lane's 16-lane row by DPP row_newbcast, pivot-row value of the lane's
+// column by one bpermute.  Lane s (s < 16) receives the pivot of step s.
+//
+// Step s as one update of every element, x <- x - c'_i r'_j, with
+//   r'_j = r_j / p (j != s), r'_s = 1 + 1/p,   c'_i = c_i (i != s), c'_s = p - 1,
+// where p is the pivot, r_j = x_sj and c_i = x_is: this yields x_ij - c_i r_j / p
+// off the pivot row and column, r_j / p on the pivot row, -c_i / p on the
+// pivot column and 1/p at the pivot, i.e. the in-place Gauss-Jordan step.
+template <typename T>
+__device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename MT<T>::v4 &Xi,
+                                               cd *pivot) {
+    typedef cplx<T> ct;
+    const int l = threadIdx.x & 63, lj = l & 15, lg = l >> 4;
+    cd pvl = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int ls = MT<T>::lg_of(s), rs = MT<T>::r_of(s);
+        const int src = s + 16 * ls;
+        const ct piv = {readlane_v(Xr[rs], src), readlane_v(Xi[rs], src)};
+        const int from = (lj + 16 * ls) << 2;
+        const ct rr = {bperm_v(from, Xr[rs]), bperm_v(from, Xi[rs])};
+        ct c[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[r] = {row_bcast_v(Xr[r], s), row_bcast_v(Xi[r], s)};
+        const ct ip = recip_fast(piv);
+        ct rp = rr * ip;
+        if (lj == s) rp = ct{T(1) + ip.re, ip.im};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            ct cf = c[r];
+            if (r == rs && lg == ls) cf.re -= T(1);
+            const ct x = fms(ct{Xr[r], Xi[r]}, cf, rp);
+            Xr[r] = x.re;
+            Xi[r] = x.im;
+        }
+        if (l == s) pvl = cd{(double)piv.re, (double)piv.im};
+    }
+    *pivot = pvl;
+}
+
 // In-place blocked Gauss-Jordan sweep without pivoting.  Contains barriers.
+//
+// The tiles rotate: at step t, Cr[p] holds tile column (p + t) mod NT and the
+// current column t is always Cr[0].  With the loop unrolled the rotation is
+// register renaming; it keeps the loop body free of run-time register
+// indexing should the loop ever be rolled to save instruction cache.
 template <typename T, int NP>
 __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
                                          typename MT<T>::v4 (&Ci)[NP / 16], GjShared<T, NP> &sh) {
@@ -279,48 +345,22 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
     for (int t = 0; t < NT; ++t) {
         if (w == t) {
 #pragma unroll
-            for (int tc = 0; tc < NT; ++tc) {
-                if (tc == t) continue;
+            for (int p = 1; p < NT; ++p) {
+                const int c = (p + t) % NT;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    sh.Rb[MT<T>::row(lg, r)][16 * tc + lj] = ct{Cr[tc][r], Ci[tc][r]};
+                    sh.Rb[MT<T>::row(lg, r)][16 * c + lj] = ct{Cr[p][r], Ci[p][r]};
             }
-            // Invert A_tt in place, in the accumulator layout (lane: column lj,
-            // rows MT<T>::row(lg, r)), by 16 scalar steps: pivot by readlane,
-            // pivot column within the lane's 16-lane row by DPP row_newbcast,
-            // pivot-row value of the lane's column by one bpermute.
-            v4 &Xr = Cr[t];
-            v4 &Xi = Ci[t];
-            cd pvl = {0.0, 0.0};
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int ls = MT<T>::lg_of(s), rs = MT<T>::r_of(s);
-                const int src = s + 16 * ls;
-                const ct piv = {readlane_v(Xr[rs], src), readlane_v(Xi[rs], src)};
-                const int from = (lj + 16 * ls) << 2;
-                const ct rr = {bperm_v(from, Xr[rs]), bperm_v(from, Xi[rs])};
-                ct c[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) c[r] = {row_bcast_v(Xr[r], s), row_bcast_v(Xi[r], s)};
-                const ct ip = recip_fast(piv);
-                const bool colj = (lj == s);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const bool me = (r == rs) && (lg == ls);
-                    const ct f = me ? ct{T(1) - ip.re, -ip.im} : c[r] * ip;
-                    ct x = fms(ct{Xr[r], Xi[r]}, f, rr);
-                    if (colj) x = me ? ip : ct{-f.re, -f.im};
-                    Xr[r] = x.re;
-                    Xi[r] = x.im;
-                }
-                if (l == s) pvl = cd{(double)piv.re, (double)piv.im};
-            }
+            v4 &Xr = Cr[0];
+            v4 &Xi = Ci[0];
+            cd pvl;
+            gj_tile_invert<T>(Xr, Xi, &pvl);
             if (l < 16) sh.pivv[16 * t + l] = pvl;
 #pragma unroll
             for (int r = 0; r < 4; ++r) sh.Tt[MT<T>::row(lg, r)][lj] = ct{Xr[r], Xi[r]};
         } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Cr[t][r], Ci[t][r]};
+            for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Cr[0][r], Ci[0][r]};
         }
         __syncthreads();
 
@@ -346,8 +386,8 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
                 Gi = MT<T>::mma(nxr, b.im, Gi);
                 Gi = MT<T>::mma(nxi, b.re, Gi);
             }
-            Cr[t] = Gr;
-            Ci[t] = Gi;
+            Cr[0] = Gr;
+            Ci[0] = Gi;
             wave_sync_lds();
 #pragma unroll
             for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Gr[r], Gi[r]};
@@ -361,18 +401,27 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
             }
         }
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) {
-            if (tc == t) continue;
+        for (int p = 1; p < NT; ++p) {
+            const int c = (p + t) % NT;
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
-                const ct b = sh.Rb[4 * k4 + lg][16 * tc + lj];
-                Cr[tc] = MT<T>::mma(gr[k4], b.re, Cr[tc]);
-                Cr[tc] = MT<T>::mma(gn[k4], b.im, Cr[tc]);
-                Ci[tc] = MT<T>::mma(gr[k4], b.im, Ci[tc]);
-                Ci[tc] = MT<T>::mma(gim[k4], b.re, Ci[tc]);
+                const ct b = sh.Rb[4 * k4 + lg][16 * c + lj];
+                Cr[p] = MT<T>::mma(gr[k4], b.re, Cr[p]);
+                Cr[p] = MT<T>::mma(gn[k4], b.im, Cr[p]);
+                Ci[p] = MT<T>::mma(gr[k4], b.im, Ci[p]);
+                Ci[p] = MT<T>::mma(gim[k4], b.re, Ci[p]);
             }
         }
         __syncthreads();
+        // rotate: the next tile column moves to Cr[0]
+        const v4 r0 = Cr[0], i0 = Ci[0];
+#pragma unroll
+        for (int p = 0; p + 1 < NT; ++p) {
+            Cr[p] = Cr[p + 1];
+            Ci[p] = Ci[p + 1];
+        }
+        Cr[NT - 1] = r0;
+        Ci[NT - 1] = i0;
     }
 }
 
