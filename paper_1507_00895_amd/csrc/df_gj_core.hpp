@@ -224,9 +224,9 @@ __device__ __forceinline__ cd row16_sum(cd x) { return {row16_sum(x.re), row16_s
 // Collatz-Wielandt bound of rho(cabs1(M) + eps I), eps = 1e-6 (it keeps every
 // component of v positive and normal in FP32 over the steps taken, and
 // raises the bound by eps at most), for M = 1 - D; uniform result across the
-// work-group.  Power steps from v = 1; after each step from
-// the second on, the bound max_i (B v)_i / v_i is formed and the loop stops
-// as soon as it is below `accept` (any positive v gives a valid bound).  The
+// work-group.  Power steps from v = 1; after each step the bound
+// max_i (B v)_i / v_i is formed and the loop stops as soon as it is below
+// `accept` (any positive v gives a valid bound).  The
 // arithmetic is FP32: every term is non-negative, so the computed sums are
 // within n * 2^-24 relative of the exact ones, and the bound is inflated by
 // (1 + 1e-5) to stay an upper bound.  Contains barriers: every thread must call.
@@ -258,7 +258,8 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
         // quarter (FP32 layout): either way one row of 16 lanes
 #pragma unroll
         for (int r = 0; r < 4; ++r) u[r] = row16_sum(u[r]);
-        const bool bound = (it >= 1);
+        // from v = 1 the first bound is the largest row sum of B
+        const bool bound = true;
         if (bound) {
             float ratio = 0.f;
 #pragma unroll
