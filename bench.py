@@ -35,20 +35,21 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workgroups: int):
     """HBM bytes per launch from the committed PMC summary, if it still matches.
 
     profiles/ladder_traffic.json records calibrated FETCH_SIZE + WRITE_SIZE of
-    one ladder launch together with a hash of the kernel's sources; when the
-    sources have changed since, the figure no longer applies and None is
-    returned.
+    the ladder kernels (one instance per launch) together with a hash of
+    their sources; when the sources have changed since, the figures no longer
+    apply and None is returned.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", "ladder_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
-        if rec.get("kernel") != kernel:
+        entry = rec["kernels"].get(f"{kernel}@{workgroups}")
+        if entry is None:
             return None
         h = hashlib.sha256()
         for name in rec["source_files"]:
@@ -56,7 +57,7 @@ def measured_traffic(kernel: str):
                 h.update(f.read())
         if h.hexdigest()[:16] != rec["source_sha256_16"]:
             return None
-        return float(rec["traffic_bytes"])
+        return float(entry["traffic_bytes"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -191,7 +192,7 @@ def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
         t_unit = 2.0 / FP32_PEAK_TFLOPS + 1.0 / FP64_PEAK_TFLOPS
         peak = 3.0 / t_unit
     return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": measured_traffic(kernel_name),
+            "frac": achieved / peak, "traffic": measured_traffic(kernel_name, 2 * n_om * N),
             "kernel": kernel_name, "variant": variant, "launch_ms": lad_ms,
             "algorithmic_flops_per_launch": flops_launch}
 
