@@ -170,7 +170,8 @@ int ladder_gjb_padded_size(int n_nu) {
     if (n_nu <= 48) return 48;
     if (n_nu <= 64) return 64;
     if (n_nu <= 96) return 96;
-    return 0;   // n_nu = 128 exceeds the register budget of one block-row per wave
+    if (n_nu <= 128) return 128;   // 8 waves; spills a little (one work-group per CU)
+    return 0;
 }
 
 bool ladder_gjb_has_occ3(int n_nu) {
@@ -186,6 +187,7 @@ hipError_t launch_ladder_gjb_f64(const LadderArgs &a, int occ, hipStream_t s) {
         case 48: return launch_gjb<48>(a, occ, s);
         case 64: return launch_gjb<64>(a, occ, s);
         case 96: return launch_gjb<96>(a, 0, s);
+        case 128: return launch_gjb<128>(a, 0, s);
         default: return hipErrorInvalidValue;
     }
 }

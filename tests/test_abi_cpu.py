@@ -153,15 +153,15 @@ def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     assert B.df_ladder_variant(64, B.DF_FP64) == "gjb"
     assert B.df_ladder_variant(64, B.DF_FP32_REFINE) == "mixed"
     assert B.df_ladder_variant(96, B.DF_FP32_REFINE) == "gjb"      # beyond the mixed kernel
-    assert B.df_ladder_variant(128, B.DF_FP64) == "vector"
+    assert B.df_ladder_variant(128, B.DF_FP64) == "gjb"
     assert B.df_ladder_variant(64, B.DF_FP32) == "fp32"
-    assert B.df_ladder_variant(128, B.DF_FP32) == "vector"
+    assert B.df_ladder_variant(128, B.DF_FP32) == "gjb"
     with pytest.raises(B.DfError):
         B.df_ladder_variant(64, B.DF_ADAPTIVE)
     B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o3")
     assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3"
     assert B.df_ladder_variant(62, B.DF_FP64) == "gjb"               # keyed by exact n_nu
-    for bad in [(96, B.DF_FP64, "gjb_o3"), (128, B.DF_FP64, "gjb"), (64, B.DF_FP64, "mixed"),
+    for bad in [(96, B.DF_FP64, "gjb_o3"), (128, B.DF_FP64, "gjb_o3"), (64, B.DF_FP64, "mixed"),
                 (64, B.DF_FP32_REFINE, "vector"), (64, B.DF_FP32_REFINE, "mixed_o3"),
                 (64, B.DF_FP32, "mixed"), (64, B.DF_FP64, "fp32_o4"), (96, B.DF_FP32, "fp32")]:
         with pytest.raises(B.DfError) as e:

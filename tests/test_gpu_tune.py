@@ -29,7 +29,8 @@ def B():
 
 
 # (D, nk, n_nu, n_om): every padded size of the certified kernels and a ragged one
-SHAPES = [(2, 8, 16, 5), (2, 8, 30, 3), (2, 16, 48, 5), (2, 8, 64, 5), (3, 4, 96, 3)]
+SHAPES = [(2, 8, 16, 5), (2, 8, 30, 3), (2, 16, 48, 5), (2, 8, 64, 5), (3, 4, 96, 3),
+          (2, 4, 128, 3), (2, 4, 112, 3)]
 
 
 def _ladder_case(B, shape, prec):
