@@ -131,7 +131,7 @@ hipError_t launch_ladder_fp64(const LadderArgs &a, hipStream_t s);
 // MFMA blocked Gauss-Jordan variant (n_nu <= 64)
 int ladder_mfma_padded_size(int n_nu);
 hipError_t launch_ladder_mfma_f64(const LadderArgs &a, hipStream_t s);
-// certified pivot-free blocked Gauss-Jordan (n_nu <= 96); occ = 3 selects the
+// certified pivot-free blocked Gauss-Jordan (n_nu <= 128); occ = 3 selects the
 // build capped at three waves per SIMD (n_nu <= 64), 0 the compiler's budget
 int ladder_gjb_padded_size(int n_nu);
 bool ladder_gjb_has_occ3(int n_nu);

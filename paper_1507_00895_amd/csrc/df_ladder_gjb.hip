@@ -141,6 +141,7 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
 
 // Two register budgets of the same kernel: the compiler's own (two
 // work-groups per CU at NP = 48, 64) and one capped for three waves per SIMD.
+// (At NP = 96 the capped build spills and measured 25 % slower: not built.)
 template <int NP>
 __global__ __launch_bounds__(NP * 4) void k_ladder_gjb_f64(LadderArgs a0) {
     gjb_body<NP>(a0);
