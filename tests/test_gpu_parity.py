@@ -291,3 +291,42 @@ def test_fused_convergence_matches_single_instance_runs(torch_dev):
                                                            use_graph=1), stream=s.cuda_stream)
         s.synchronize()
         assert np.array_equal(host(one.sigma), host(x.sigma))
+
+
+def test_batched_uneven_workload_full_size_sampled(torch_dev):
+    """The batched uneven workload at full size: 64 seeded instances (D in {2,3},
+    2D 16^2..64^2, 3D 8^3..16^3, n_nu in {32, 64, 128}) in one fused iteration,
+    as a serving call would run them.  Per instance: G~ in full; W at q = 0 and
+    one seeded q against the oracle ladder; for one instance of each
+    (D, nk, n_nu) class also chi~ and Sigma~calc (from the GPU's W) in full."""
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    params = I.draw_batched_params()
+    probs = I.batched_problems(params)
+    insts = [B.make_instance(p) for p in probs]
+    ws = B.workspace(insts)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    code, iters, _ = B.df_iterate(insts, ws, B.make_opts(mix=0.5, max_iter=1, use_graph=1),
+                                  stream=s.cuda_stream)
+    s.synchronize()
+    assert iters == 1
+    rng = np.random.default_rng(64)
+    seen = set()
+    for p, x in zip(probs, insts):
+        gd = host(x.gd)
+        G0 = O.dual_gf0(p.g, p.delta, p.eps)
+        assert rel(gd, O.dual_gf(G0, np.zeros_like(G0))) <= TOL64, p.summary()
+        chi = host(x.chi)
+        qs = np.array([0, int(rng.integers(1, p.N))])
+        lr = O.ladder(O.spin_channels(p.gamma_uu, p.gamma_ud), chi[:, :, qs])
+        W = host(x.w)
+        assert np.array_equal(host(x.status)[:, :, qs], lr.status), p.summary()
+        assert rel(W[..., qs], lr.W) <= TOL64, p.summary()
+        key = (p.D, p.nk, p.n_nu)
+        if key in seen:
+            continue
+        seen.add(key)
+        assert rel(chi, O.bubble_fft(gd, p.D, p.nk, p.n_om, p.beta)) <= TOL64, p.summary()
+        assert rel(host(x.sigma_calc), O.sigma_fft(W, gd, p.D, p.nk, p.beta)) <= TOL64, p.summary()
+    assert len(seen) >= 10
