@@ -220,6 +220,11 @@ __device__ __forceinline__ double row16_sum(double x) {
     return x;
 }
 __device__ __forceinline__ cd row16_sum(cd x) { return {row16_sum(x.re), row16_sum(x.im)}; }
+// Sum over the wave, returned uniform: row sums, then the four row leaders.
+__device__ __forceinline__ double wave_sum(double x) {
+    x = row16_sum(x);
+    return (readlane_v(x, 0) + readlane_v(x, 16)) + (readlane_v(x, 32) + readlane_v(x, 48));
+}
 
 // Collatz-Wielandt bound of rho(cabs1(M) + eps I), eps = 1e-6 (it keeps every
 // component of v positive and normal in FP32 over the steps taken, and
@@ -437,11 +442,8 @@ __device__ __forceinline__ int gj_logdet(const cd *pivv, cd *out_logdet) {
         lre += log(hypot(pv.re, pv.im));
         lim += atan2(pv.im, pv.re);
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        lre += __shfl_xor(lre, off, 64);
-        lim += __shfl_xor(lim, off, 64);
-    }
+    lre = wave_sum(lre);
+    lim = wave_sum(lim);
     double ph = remainder(lim, 2.0 * M_PI);
     if (ph <= -M_PI) ph += 2.0 * M_PI;
     *out_logdet = cd{lre, ph};

@@ -100,21 +100,29 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
     __syncthreads();
     const int stt = s_flag;
 
-    // ---- Gamma_nn = sum_l (D^-1)_nl gamma_ln  (gamma^T read row-wise)
+    // ---- Gamma_nn = sum_l (D^-1)_nl gamma_ln  (gamma^T read row-wise); loads
+    // per tile column without branches (clamped indices, padding masked)
     if (stt == 0) {
+        const int nm1 = n_nu - 1;
+        // an opaque copy of the row base keeps the compiler from sharing these
+        // indices with the identical ones of the D build, which would hold them
+        // in registers across the sweep
+        int row0 = 16 * w, col0 = lj;
+        asm volatile("" : "+v"(row0), "+v"(col0));
         cd yp[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            yp[r] = {0.0, 0.0};
-            const int i = 16 * w + MT<double>::row(lg, r);
-            if (i < n_nu) {
+        for (int r = 0; r < 4; ++r) yp[r] = {0.0, 0.0};
 #pragma unroll
-                for (int tc = 0; tc < NT; ++tc) {
-                    const int j = 16 * tc + lj;
-                    if (j < n_nu)
-                        yp[r] = fma_c(yp[r], cd{Cr[tc][r], Ci[tc][r]},
-                                      ld(gtr, (size_t)i * n_nu + j));
-                }
+        for (int tc = 0; tc < NT; ++tc) {
+            const int j = 16 * tc + col0;
+            cd gv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                gv[r] = ld(gtr, (size_t)min(row0 + MT<double>::row(lg, r), nm1) * n_nu + min(j, nm1));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool in = (row0 + MT<double>::row(lg, r) < n_nu) && (j < n_nu);
+                yp[r] = fma_c(yp[r], cd{Cr[tc][r], Ci[tc][r]}, in ? gv[r] : cd{0.0, 0.0});
             }
         }
 #pragma unroll

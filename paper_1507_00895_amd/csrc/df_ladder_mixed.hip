@@ -139,21 +139,29 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
 
     if constexpr (!REFINE) {
         if (stt == 0) {
-            // ---- Gamma_nn = sum_l X_nl gamma_ln  (gamma^T read row-wise)
+            // ---- Gamma_nn = sum_l X_nl gamma_ln  (gamma^T read row-wise); loads
+            // per tile column without branches.  Opaque copies of the row and
+            // column bases keep the compiler from sharing these indices with
+            // those of the D build (which would hold them across the sweep).
             const double *gtr = a.gtr + 2 * (size_t)cm * nn;
+            const int nm1 = n_nu - 1;
+            int row0 = 16 * w, col0 = lj;
+            asm volatile("" : "+v"(row0), "+v"(col0));
             cd yp[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                yp[r] = {0.0, 0.0};
-                const int i = 16 * w + MT<float>::row(lg, r);
-                if (i < n_nu) {
+            for (int r = 0; r < 4; ++r) yp[r] = {0.0, 0.0};
 #pragma unroll
-                    for (int tc = 0; tc < NT; ++tc) {
-                        const int j = 16 * tc + lj;
-                        if (j < n_nu)
-                            yp[r] = fma_c(yp[r], cd{(double)Cr[tc][r], (double)Ci[tc][r]},
-                                          ld(gtr, (size_t)i * n_nu + j));
-                    }
+            for (int tc = 0; tc < NT; ++tc) {
+                const int j = 16 * tc + col0;
+                cd gv[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    gv[r] = ld(gtr, (size_t)min(row0 + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool in = (row0 + MT<float>::row(lg, r) < n_nu) && (j < n_nu);
+                    yp[r] = fma_c(yp[r], cd{(double)Cr[tc][r], (double)Ci[tc][r]},
+                                  in ? gv[r] : cd{0.0, 0.0});
                 }
             }
 #pragma unroll
