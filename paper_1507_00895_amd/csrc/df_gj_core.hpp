@@ -241,8 +241,7 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
                                              GjShared<T, NP> &sh, int iters, double accept) {
     constexpr int NT = NP / 16;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
-    for (int i = tid; i < NP; i += NP * 4) sh.vbuf[0][i] = 1.0;
-    __syncthreads();
+    // step 0 starts from v = 1 without reading it (no barrier before it)
     double cw = INFINITY;
     for (int it = 0; it < iters; ++it) {
         const double *v = sh.vbuf[it & 1];
@@ -250,7 +249,7 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
 #pragma unroll
         for (int tc = 0; tc < NT; ++tc) {
             const int j = 16 * tc + lj;
-            const float vj = (float)v[j];
+            const float vj = (it == 0) ? 1.0f : (float)v[j];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 16 * w + MT<T>::row(lg, r);
@@ -269,7 +268,8 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
             float ratio = 0.f;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float rr = u[r] * __builtin_amdgcn_rcpf((float)v[16 * w + MT<T>::row(lg, r)]);
+                const float vi = (it == 0) ? 1.0f : (float)v[16 * w + MT<T>::row(lg, r)];
+                const float rr = u[r] * __builtin_amdgcn_rcpf(vi);
                 ratio = rr > ratio ? rr : ratio;
             }
             const double m = wave_max_pos((double)ratio);
