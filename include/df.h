@@ -120,7 +120,15 @@ typedef struct {
  *               fixed point, and the FP64 iterations that follow contract it
  *               away with the rest, so the converged Sigma~ is that of DF_FP64.
  *   use_graph   nonzero: df_iterate captures one iteration in a hipGraph and replays it
- *   reserved    zero
+ *   accel       0: linear mixing, Sigma <- (1 - mix) Sigma + mix Sigma_calc.
+ *               1..8: Anderson acceleration over the last accel + 1 iterates:
+ *               Sigma <- sum_j c_j (Sigma_j + mix (Sigma_calc_j - Sigma_j)), with
+ *               real weights c_j (summing to one) from the least-squares fit of
+ *               the newest residual by differences of recorded residuals.  Real
+ *               weights keep Sigma~(-nu) = Sigma~(nu)* and the lattice
+ *               symmetries.  Same fixed point, fewer iterations.  The workspace
+ *               grows by (2 accel + 3) n_nu N complex per instance: size it with
+ *               the same options.
  */
 typedef struct {
     int32_t prec;
@@ -129,7 +137,7 @@ typedef struct {
     double tol;
     double switch_tol;
     int32_t use_graph;
-    int32_t reserved;
+    int32_t accel;
 } df_opts_t;
 
 /* Workspace bytes needed by any entry point for these instances and options. */

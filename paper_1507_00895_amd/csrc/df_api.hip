@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <utility>
 #include <vector>
 
 #include "../../include/df.h"
@@ -63,10 +64,13 @@ int check_inst(const df_inst_t &p, Shape *s) {
 
 // Per-instance workspace regions (byte offsets from the instance base).
 struct Layout {
-    size_t gr, gdm, pdm, gtr, part, norm, gd, chi, w, total;
+    size_t gr, gdm, pdm, gtr, part, norm, gd, chi, w;
+    size_t fx, xh, rh, accpart;       // Anderson acceleration (0 when unused)
+    size_t total;
 };
 
-Layout layout_of(const Shape &s) {
+// slots: ring length of the Anderson acceleration, 0 for linear mixing
+Layout layout_of(const Shape &s, int slots) {
     Layout L;
     const size_t cdb = 16;
     size_t o = 0;
@@ -86,6 +90,13 @@ Layout layout_of(const Shape &s) {
     L.gd = take(fld);
     L.chi = take((size_t)s.n_om * fld);
     L.w = take(2 * (size_t)s.n_om * fld);
+    L.fx = L.xh = L.rh = L.accpart = 0;
+    if (slots > 0) {
+        L.fx = take(fld);
+        L.xh = take((size_t)slots * fld);
+        L.rh = take((size_t)slots * fld);
+        L.accpart = take((size_t)kMixBlocks * kAccMaxSlots * sizeof(double));
+    }
     L.total = o;
     return L;
 }
@@ -96,6 +107,7 @@ struct Global {
     size_t queue;                     // int[sum of items]: uncertified items
     size_t ints;                      // int[kMaxClasses + n_inst]: queue lengths, outside counts
     size_t diffs;                     // double[n_inst][2]: diff, non-finite flag
+    size_t accdots;                   // double[n_inst][kAccMaxSlots] (Anderson)
     size_t total;
 };
 
@@ -107,7 +119,9 @@ struct Plan {
     size_t total = 0;
 };
 
-int make_plan(const df_inst_t *inst, int32_t n_inst, Plan *P) {
+// accel: Anderson history depth of df_iterate (0: linear mixing); it sizes
+// the extra workspace regions
+int make_plan(const df_inst_t *inst, int32_t n_inst, Plan *P, int accel = 0) {
     if (!inst || n_inst < 1) return DF_E_INVAL;
     P->shape.resize(n_inst);
     P->lay.resize(n_inst);
@@ -117,7 +131,7 @@ int make_plan(const df_inst_t *inst, int32_t n_inst, Plan *P) {
     for (int i = 0; i < n_inst; ++i) {
         const int rc = check_inst(inst[i], &P->shape[i]);
         if (rc != DF_OK) return rc;
-        P->lay[i] = layout_of(P->shape[i]);
+        P->lay[i] = layout_of(P->shape[i], accel > 0 ? accel + 1 : 0);
         P->base[i] = off;
         off = align_up(off + P->lay[i].total);
         items += (size_t)P->shape[i].items;
@@ -132,6 +146,8 @@ int make_plan(const df_inst_t *inst, int32_t n_inst, Plan *P) {
     off = align_up(off + (size_t)(kMaxClasses + n_inst) * sizeof(int));
     g.diffs = off;
     off = align_up(off + (size_t)n_inst * 2 * sizeof(double));
+    g.accdots = off;
+    off = align_up(off + (size_t)n_inst * kAccMaxSlots * sizeof(double));
     g.total = off;
     P->total = off;
     return DF_OK;
@@ -334,7 +350,7 @@ bool ladder_prec(int prec) { return prec == DF_FP64 || prec == DF_FP32_REFINE ||
 int check_opts(const df_opts_t *o, bool need_loop, bool adaptive) {
     if (!o) return need_loop ? DF_E_INVAL : DF_OK;
     if (!ladder_prec(o->prec) && !(adaptive && o->prec == DF_ADAPTIVE)) return DF_E_INVAL;
-    if (o->reserved != 0 || !isfinite(o->switch_tol)) return DF_E_INVAL;
+    if (o->accel < 0 || o->accel > kAccMaxSlots - 1 || !isfinite(o->switch_tol)) return DF_E_INVAL;
     if (need_loop) {
         if (!(o->mix > 0.0 && o->mix <= 1.0)) return DF_E_INVAL;
         if (o->max_iter < 1) return DF_E_INVAL;
@@ -451,11 +467,94 @@ int queue_fused_iteration(const df_inst_t *inst, const Plan &P, const Fused &F,
         double *w = inst[i].w ? inst[i].w : at<double>(ws, b + L.w);
         rc = stage_sigma(inst[i], s, w, gr, part, st);
         if (rc != DF_OK) return rc;
-        rc = stage_reduce_mix(s, part, inst[i].sigma_calc, inst[i].sigma, o.mix,
-                              at<double>(ws, b + L.norm), at<double>(ws, P.g.diffs) + 2 * i, st);
+        if (o.accel > 0) {
+            // F(x) only; the accelerated step follows outside this sequence
+            rc = stage_reduce_mix(s, part, at<double>(ws, b + L.fx), nullptr, 0.0, nullptr, nullptr,
+                                  st);
+        } else {
+            rc = stage_reduce_mix(s, part, inst[i].sigma_calc, inst[i].sigma, o.mix,
+                                  at<double>(ws, b + L.norm), at<double>(ws, P.g.diffs) + 2 * i, st);
+        }
         if (rc != DF_OK) return rc;
     }
     return DF_OK;
+}
+
+// ---- Anderson acceleration, host side -----------------------------------------
+int mix_blocks(const Shape &s) {
+    const size_t count = (size_t)s.n_nu * s.N;
+    int blocks = (int)((count + 255) / 256);
+    return blocks > kMixBlocks ? kMixBlocks : blocks;
+}
+
+// State of one instance: how many residuals are recorded since the last
+// reset (slots fill 0, 1, ... and then wrap), and the Gram matrix of the
+// recorded residuals, Re <r_i, r_j>, indexed by slot.
+struct AccState {
+    int recorded = 0;
+    std::vector<double> gram;
+};
+
+// Solve the n x n system A y = b in place (partial pivoting); false if singular.
+bool small_solve(std::vector<double> &A, std::vector<double> &b, int n) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r * n + c]) > fabs(A[piv * n + c])) piv = r;
+        if (!(fabs(A[piv * n + c]) > 0.0) || !isfinite(A[piv * n + c])) return false;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double v = b[c];
+        for (int k = c + 1; k < n; ++k) v -= A[c * n + k] * b[k];
+        b[c] = v / A[c * n + c];
+        if (!isfinite(b[c])) return false;
+    }
+    return true;
+}
+
+// Weights c_j of the accelerated iterate x' = sum_j c_j (x_j + alpha r_j) over
+// the recorded slots: least squares of the newest residual against the
+// differences of consecutive residuals (real coefficients).  Returns false
+// (and the plain mixing step) when the system is singular.
+bool acc_weights(const AccState &S, int slots, int newest, double *coef) {
+    const int h = S.recorded < slots ? S.recorded : slots;   // slots in use
+    for (int j = 0; j < kAccMaxSlots; ++j) coef[j] = 0.0;
+    coef[newest] = 1.0;
+    if (h < 2) return true;
+    std::vector<int> ord(h);                                  // oldest .. newest
+    for (int a = 0; a < h; ++a) ord[a] = ((newest - (h - 1 - a)) % slots + slots) % slots;
+    const int n = h - 1;
+    auto G = [&](int i, int j) { return S.gram[ord[i] * slots + ord[j]]; };
+    std::vector<double> A((size_t)n * n), rhs(n);
+    double tr = 0.0;
+    for (int a = 0; a < n; ++a) {
+        for (int c = 0; c < n; ++c)
+            A[a * n + c] = G(a + 1, c + 1) - G(a + 1, c) - G(a, c + 1) + G(a, c);
+        rhs[a] = G(a + 1, h - 1) - G(a, h - 1);
+        tr += A[a * n + a];
+    }
+    const double lam = 1e-12 * (tr > 0.0 ? tr / n : 1.0);
+    for (int a = 0; a < n; ++a) A[a * n + a] += lam;
+    if (!small_solve(A, rhs, n)) return false;
+    // x' = x_newest - sum_a y_a (x_{a+1} - x_a), same weights for r
+    coef[newest] = 0.0;
+    for (int a = 0; a < h; ++a) {
+        double c = 0.0;
+        if (a < n) c += rhs[a];
+        if (a > 0) c -= rhs[a - 1];
+        if (a == h - 1) c += 1.0;
+        coef[ord[a]] = c;
+    }
+    return true;
 }
 
 }  // namespace
@@ -483,7 +582,7 @@ int df_workspace_size(const df_inst_t *inst, int32_t n_inst, const df_opts_t *op
     int rc = check_opts(opts, false, true);
     if (rc != DF_OK) return rc;
     Plan P;
-    rc = make_plan(inst, n_inst, &P);
+    rc = make_plan(inst, n_inst, &P, opts ? opts->accel : 0);
     if (rc != DF_OK) return rc;
     *bytes = P.total;
     return DF_OK;
@@ -605,7 +704,7 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     int rc = check_opts(opts, true, true);
     if (rc != DF_OK) return rc;
     Plan P;
-    rc = make_plan(inst, n_inst, &P);
+    rc = make_plan(inst, n_inst, &P, opts->accel);
     if (rc != DF_OK) return rc;
     rc = check_ws(P, ws, ws_bytes);
     if (rc != DF_OK) return rc;
@@ -613,6 +712,10 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
         const df_inst_t &p = inst[i];
         if (!p.g || !p.delta || !p.eps || !p.gamma_uu || !p.gamma_ud || !p.sigma) return DF_E_INVAL;
     }
+    const int slots = opts->accel > 0 ? opts->accel + 1 : 0;
+    std::vector<AccState> acc(slots > 0 ? n_inst : 0);
+    for (auto &S : acc) S.gram.assign((size_t)slots * slots, 0.0);
+    std::vector<double> hdots((size_t)n_inst * kAccMaxSlots);
     rc = ensure_attrs();
     if (rc != DF_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -675,6 +778,70 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
             if (rc != DF_OK) return rc;
         }
         ++it;
+        if (slots > 0) {
+            // record x_k, r_k and their dots; weights on the host; the step
+            for (int i : act) {
+                const Shape &sh = P.shape[i];
+                const Layout &L = P.lay[i];
+                const size_t b = P.base[i];
+                AccRecordArgs ra{};
+                ra.count = (size_t)sh.n_nu * sh.N;
+                ra.x = inst[i].sigma;
+                ra.fx = at<double>(ws, b + L.fx);
+                ra.xh = at<double>(ws, b + L.xh);
+                ra.rh = at<double>(ws, b + L.rh);
+                ra.slot = acc[i].recorded % slots;
+                ra.n_slots = acc[i].recorded + 1 < slots ? acc[i].recorded + 1 : slots;
+                ra.part = at<double>(ws, b + L.accpart);
+                ra.dots = at<double>(ws, P.g.accdots) + (size_t)i * kAccMaxSlots;
+                if (launch_acc_record(ra, mix_blocks(sh), st) != hipSuccess) {
+                    cleanup();
+                    return DF_E_HIP;
+                }
+            }
+            if (hipMemcpyAsync(hdots.data(), at<double>(ws, P.g.accdots),
+                               hdots.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                cleanup();
+                return DF_E_HIP;
+            }
+            for (int i : act) {
+                AccState &S = acc[i];
+                const int slot = S.recorded % slots;
+                const int nv = S.recorded + 1 < slots ? S.recorded + 1 : slots;
+                for (int j = 0; j < nv; ++j) {
+                    const double d = hdots[(size_t)i * kAccMaxSlots + j];
+                    S.gram[slot * slots + j] = d;
+                    S.gram[j * slots + slot] = d;
+                }
+                ++S.recorded;
+                AccCombineArgs ca{};
+                const bool ok = acc_weights(S, slots, slot, ca.coef);
+                if (!ok) {
+                    // plain mixing step; the history restarts from this iterate
+                    for (int j = 0; j < kAccMaxSlots; ++j) ca.coef[j] = (j == slot) ? 1.0 : 0.0;
+                }
+                const Shape &sh = P.shape[i];
+                const Layout &L = P.lay[i];
+                const size_t b = P.base[i];
+                ca.count = (size_t)sh.n_nu * sh.N;
+                ca.xh = at<double>(ws, b + L.xh);
+                ca.rh = at<double>(ws, b + L.rh);
+                ca.n_slots = nv;
+                ca.alpha = opts->mix;
+                ca.x = inst[i].sigma;
+                ca.norm_part = at<double>(ws, b + L.norm);
+                const int blocks = mix_blocks(sh);
+                if (launch_acc_combine(ca, blocks, st) != hipSuccess ||
+                    launch_norm_final(ca.norm_part, blocks, at<double>(ws, P.g.diffs) + 2 * i, st) !=
+                        hipSuccess) {
+                    cleanup();
+                    return DF_E_HIP;
+                }
+                if (!ok) S.recorded = 0;
+            }
+        }
         if (hipMemcpyAsync(hdiff.data(), at<double>(ws, P.g.diffs), hdiff.size() * sizeof(double),
                            hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipMemcpyAsync(hints.data(), at<int>(ws, P.g.ints), hints.size() * sizeof(int),
@@ -702,6 +869,7 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
                  hdiff[2 * i] > 0.95 * prev)) {
                 cur[i] = DF_FP64;
                 rebuild = true;
+                if (slots > 0) acc[i].recorded = 0;   // FP32 residuals leave the history
                 next.push_back(i);
                 continue;
             }
@@ -713,6 +881,17 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
         act.swap(next);
     }
     cleanup();
+    if (slots > 0) {
+        // sigma_calc (F of the last iterate) where the caller asked for it
+        for (int i = 0; i < n_inst; ++i) {
+            if (!inst[i].sigma_calc) continue;
+            const Shape &sh = P.shape[i];
+            if (hipMemcpyAsync(inst[i].sigma_calc, at<double>(ws, P.base[i] + P.lay[i].fx),
+                               (size_t)sh.n_nu * sh.N * 16, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return DF_E_HIP;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) return DF_E_HIP;
+    }
     if (iters_out) *iters_out = it;
     if (diff_out)
         for (int i = 0; i < n_inst; ++i) diff_out[i] = last[i];

@@ -48,6 +48,28 @@ struct ReduceMixArgs {
     double *norm_part;               // [gridDim][2]
 };
 
+// Anderson acceleration (df_accel.hip): ring of up to kAccMaxSlots iterates
+constexpr int kAccMaxSlots = 9;
+
+struct AccRecordArgs {
+    size_t count;                    // n_nu * N complex elements
+    const double *x, *fx;            // current iterate, F(iterate)
+    double *xh, *rh;                 // rings [kAccMaxSlots][count]
+    int slot, n_slots;               // slot written now; slots in use (incl. it)
+    double *part;                    // [blocks][kAccMaxSlots] partial dots
+    double *dots;                    // [kAccMaxSlots]: Re <r_j, r_slot>
+};
+
+struct AccCombineArgs {
+    size_t count;
+    const double *xh, *rh;
+    int n_slots;
+    double coef[kAccMaxSlots];       // real weights, summing to one
+    double alpha;
+    double *x;                       // in: x_k, out: x_{k+1}
+    double *norm_part;               // [blocks][2]
+};
+
 struct GammaPrepArgs {
     int n_nu, n_om;
     const double *guu, *gud;
@@ -122,6 +144,8 @@ hipError_t launch_bubble(const BubbleArgs &a, hipStream_t s);
 hipError_t launch_sigma_part(const SigmaArgs &a, hipStream_t s);
 hipError_t launch_reduce_mix(const ReduceMixArgs &a, int blocks, hipStream_t s);
 hipError_t launch_norm_final(const double *part, int n_part, double *out, hipStream_t s);
+hipError_t launch_acc_record(const AccRecordArgs &a, int blocks, hipStream_t s);
+hipError_t launch_acc_combine(const AccCombineArgs &a, int blocks, hipStream_t s);
 hipError_t launch_gamma_prep(const GammaPrepArgs &a, hipStream_t s);
 hipError_t set_fft_lds_limits();
 

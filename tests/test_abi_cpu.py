@@ -51,7 +51,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(df_inst_t), offsetof(df_inst_t, beta),
          offsetof(df_inst_t, g), offsetof(df_inst_t, status), sizeof(df_opts_t),
          offsetof(df_opts_t, max_iter), offsetof(df_opts_t, tol), offsetof(df_opts_t, switch_tol),
-         offsetof(df_opts_t, reserved));
+         offsetof(df_opts_t, accel));
   return 0;
 }
 ''')
@@ -61,7 +61,7 @@ int main(void) {
                                            check=True).stdout.split()]
     assert vals == [ctypes.sizeof(B.DfInst), B.DfInst.beta.offset, B.DfInst.g.offset,
                     B.DfInst.status.offset, ctypes.sizeof(B.DfOpts), B.DfOpts.max_iter.offset,
-                    B.DfOpts.tol.offset, B.DfOpts.switch_tol.offset, B.DfOpts.reserved.offset]
+                    B.DfOpts.tol.offset, B.DfOpts.switch_tol.offset, B.DfOpts.accel.offset]
 
 
 def _inst(**kw):
@@ -108,9 +108,13 @@ def test_workspace_size_and_validation_order():
     ad = B.make_opts(prec=B.DF_ADAPTIVE)
     assert lib.df_ladder_solve(arr, 1, ctypes.byref(ad), 0x1000, n.value, None) == B.DF_E_INVAL
     assert lib.df_workspace_size(arr, 1, ctypes.byref(ad), ctypes.byref(n)) == B.DF_OK
-    bad = B.make_opts()
-    bad.reserved = 1
+    bad = B.make_opts(accel=9)
     assert lib.df_ladder_solve(arr, 1, ctypes.byref(bad), 0x1000, n.value, None) == B.DF_E_INVAL
+    # Anderson history needs workspace
+    m0, m5 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.df_workspace_size(arr, 1, ctypes.byref(B.make_opts()), ctypes.byref(m0)) == B.DF_OK
+    assert lib.df_workspace_size(arr, 1, ctypes.byref(B.make_opts(accel=5)), ctypes.byref(m5)) == B.DF_OK
+    assert m5.value >= m0.value + 13 * 16 * 64 * 16
     assert B.df_strerror(B.DF_E_WORKSPACE).startswith("workspace")
     assert B.df_version() >= 100
 
