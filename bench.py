@@ -14,10 +14,10 @@ whole iterations of the --prec path; beside it: the ladder kernel's own rate
 and roofline, and under "paths" the ladder rate and seconds per converged
 Sigma~ (tol 1e-8) of the plain FP64 path, the per-ladder mixed-precision
 path (FP32 + FP64 residual correction), the adaptive path (FP32 ladders while
-the diff exceeds 1e-4, FP64 after), and both FP64 and adaptive paths
-warm-started by the learned network (trained inside the run on converged
-Sigma~ of the same shape; its cost is reported separately), and the CPU
-oracle rate.  Progress goes to stderr.
+the diff exceeds 1e-4, FP64 after), the FP64 and adaptive paths with Anderson
+acceleration of the mixing, and paths warm-started by the learned network
+(trained inside the run on converged Sigma~ of the same shape; its cost is
+reported separately), and the CPU oracle rate.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 matrix (= FP64 vector) peak
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 matrix peak
+ACCEL = 5                    # Anderson history depth of the accelerated paths
 HBM_PEAK_GBS = 8000.0
 
 
@@ -78,9 +79,9 @@ def parse():
                     help="skip the seconds-per-converged-Sigma~ legs of all paths")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-started path")
     ap.add_argument("--no-tune", action="store_true", help="keep the default ladder kernels")
-    ap.add_argument("--warm-train", type=int, default=48,
+    ap.add_argument("--warm-train", type=int, default=96,
                     help="converged instances the warm-start network is trained on")
-    ap.add_argument("--warm-steps", type=int, default=2000)
+    ap.add_argument("--warm-steps", type=int, default=4000)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
@@ -149,9 +150,10 @@ def ladder_launch_ms(B, insts, ws, prec, stream, reps):
     return float(np.mean(ms)) / len(insts)
 
 
-def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None):
+def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None, accel=0):
     """Cold (or given) start to tol 1e-8, one instance at a time (DF_ADAPTIVE:
-    FP32 ladders down to a diff of 1e-4, FP64 after)."""
+    FP32 ladders down to a diff of 1e-4, FP64 after; accel > 0: Anderson
+    acceleration over accel + 1 iterates)."""
     import torch
     out = []
     for i, (p, x) in enumerate(zip(problems, insts)):
@@ -162,7 +164,8 @@ def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None):
         torch.cuda.synchronize()
         ta = time.perf_counter()
         code, it, d = B.df_iterate([x], ws, B.make_opts(prec=prec, mix=0.5, tol=1e-8, max_iter=500,
-                                                        use_graph=graph, switch_tol=1e-4),
+                                                        use_graph=graph, switch_tol=1e-4,
+                                                        accel=accel),
                                    stream=stream.cuda_stream,
                                    allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
         stream.synchronize()
@@ -204,8 +207,8 @@ def warm_start_leg(problems, args, log):
     p = problems[0]
     cfg = W.WarmStartConfig(nk=p.nk, n_nu=p.n_nu, n_om=p.n_om, t=p.t)
     t0 = time.perf_counter()
-    ptrain = W.draw(args.warm_train, 895, cfg)
-    sig, _, _ = W.converge(ptrain, cfg)
+    ptrain = W.draw(args.warm_train, 895, cfg, corners=True)
+    sig, _, _ = W.converge(ptrain, cfg, accel=ACCEL)   # same fixed points, fewer iterations
     t_data = time.perf_counter() - t0
     X = W.build_features(ptrain, cfg)
     Y = W.targets_from_sigma(sig, cfg)
@@ -246,7 +249,8 @@ def main():
     problems = I.workload_square32()
     insts = [B.make_instance(p, device=dev) for p in problems]
     prec = {"fp64": B.DF_FP64, "mixed": B.DF_FP32_REFINE, "fp32": B.DF_FP32}[args.prec]
-    opts = B.make_opts(prec=prec, mix=0.5, tol=0.0, max_iter=1, use_graph=args.graph)
+    opts = B.make_opts(prec=prec, mix=0.5, tol=0.0, max_iter=1, use_graph=args.graph,
+                       accel=ACCEL)
     ws = B.workspace(insts, opts, device=dev)
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
@@ -314,10 +318,18 @@ def main():
                               "converged": conv})
                 log(f"{name}: {entry['s_per_converged_sigma']:.3f} s per converged Sigma~")
             paths[name] = entry
+        # the same loops with Anderson acceleration of the mixing
+        for name, pr in (("fp64_anderson", B.DF_FP64), ("adaptive_anderson", B.DF_ADAPTIVE)):
+            conv = converge_each(B, problems, insts, ws, pr, stream, args.graph, accel=ACCEL)
+            paths[name] = {"s_per_converged_sigma": float(np.mean([c["seconds"] for c in conv])),
+                           "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
+                           "accel": ACCEL, "converged": conv}
+            log(f"{name}: {paths[name]['s_per_converged_sigma']:.3f} s per converged Sigma~")
         if not args.no_warm:
             sigma0, info = warm_start_leg(problems, args, log)
-            for name, pr in (("warm_fp64", B.DF_FP64), ("warm_adaptive", B.DF_ADAPTIVE)):
-                conv = converge_each(B, problems, insts, ws, pr, stream, args.graph, sigma0)
+            for name, pr, ac in (("warm_fp64", B.DF_FP64, 0), ("warm_adaptive", B.DF_ADAPTIVE, 0),
+                                 ("warm_adaptive_anderson", B.DF_ADAPTIVE, ACCEL)):
+                conv = converge_each(B, problems, insts, ws, pr, stream, args.graph, sigma0, accel=ac)
                 sec = float(np.mean([c["seconds"] for c in conv])) + info["inference_seconds_per_instance"]
                 paths[name] = {"s_per_converged_sigma": sec,
                                "mean_iterations": float(np.mean([c["iterations"] for c in conv])),

@@ -52,8 +52,10 @@ class WarmStartConfig:
         return I.atomic_limit_problem(2, self.nk, self.n_nu, self.n_om, beta, U, self.t)
 
 
-def draw(n: int, seed: int, cfg: WarmStartConfig):
-    """n (U, beta) pairs, Latin-hypercube stratified over the two ranges."""
+def draw(n: int, seed: int, cfg: WarmStartConfig, corners: bool = False):
+    """n (U, beta) pairs, Latin-hypercube stratified over the two ranges; with
+    corners, the four corners of the (U, beta) box replace four of them (a
+    network interpolates poorly towards corners it has not seen)."""
     rng = np.random.default_rng(seed)
     out = []
     cols = []
@@ -62,6 +64,9 @@ def draw(n: int, seed: int, cfg: WarmStartConfig):
         cols.append(lo + (hi - lo) * u)
     for U, beta in zip(*cols):
         out.append((float(U), float(beta)))
+    if corners and n >= 8:
+        (u0, u1), (b0, b1) = cfg.U_range, cfg.beta_range
+        out[:4] = [(u0, b0), (u0, b1), (u1, b0), (u1, b1)]
     return out
 
 
@@ -114,8 +119,9 @@ def build_features(params: List[tuple], cfg: WarmStartConfig, device="cuda") -> 
 
 # ---------------------------------------------------------------- data from the method
 def converge(params: List[tuple], cfg: WarmStartConfig, sigma0: Optional[list] = None,
-             batch: int = 64, device="cuda"):
-    """Run df_iterate to cfg.tol for every instance (fused batches).
+             batch: int = 64, device="cuda", accel: int = 0):
+    """Run df_iterate to cfg.tol for every instance (fused batches; accel > 0:
+    Anderson-accelerated, same fixed point).
 
     Returns (sigma list [n_nu x N] numpy, iteration counts, seconds per batch).
     """
@@ -129,11 +135,11 @@ def converge(params: List[tuple], cfg: WarmStartConfig, sigma0: Optional[list] =
         if sigma0 is not None:
             for x, s0 in zip(insts, sigma0[s:s + batch]):
                 x.sigma.copy_(torch.as_tensor(s0))
-        ws = B.workspace(insts, device=device)
+        ws = B.workspace(insts, B.make_opts(accel=accel), device=device)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         code, it, diffs = B.df_iterate(insts, ws, B.make_opts(mix=cfg.mix, tol=cfg.tol, max_iter=500,
-                                                              use_graph=1),
+                                                              use_graph=1, accel=accel),
                                        stream=stream.cuda_stream,
                                        allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
         stream.synchronize()
@@ -243,8 +249,9 @@ def train_and_evaluate(n_train: int = 256, n_test: int = 16, steps: int = 2000,
     cfg = cfg or WarmStartConfig()
     N = cfg.nk ** 2
     t0 = time.perf_counter()
-    ptrain = draw(n_train, seed_train, cfg)
-    sig, its_train, _ = converge(ptrain, cfg, device=device)
+    ptrain = draw(n_train, seed_train, cfg, corners=True)
+    # training data: the method's own fixed points (accelerated loop, same fixed point)
+    sig, its_train, _ = converge(ptrain, cfg, device=device, accel=5)
     t_data = time.perf_counter() - t0
     log(f"warm start: {n_train} converged training instances in {t_data:.1f} s")
     X = build_features(ptrain, cfg, device)
