@@ -64,7 +64,7 @@ int check_inst(const df_inst_t &p, Shape *s) {
 
 // Per-instance workspace regions (byte offsets from the instance base).
 struct Layout {
-    size_t gr, gdm, pdm, gtr, part, norm, gd, chi, w;
+    size_t gr, gdm, pdm, gtr, gp32, gtr32, part, norm, gd, chi, w;
     size_t fx, xh, rh, accpart;       // Anderson acceleration (0 when unused)
     size_t total;
 };
@@ -85,6 +85,8 @@ Layout layout_of(const Shape &s, int slots) {
     L.gdm = take(gam);
     L.pdm = take(gam);
     L.gtr = take(gam);
+    L.gp32 = take(gam);              // (gamma, gamma_ij gamma_ji) as 4 floats
+    L.gtr32 = take(gam / 2);
     L.part = take((size_t)s.n_chunks * fld);
     L.norm = take((size_t)kMixBlocks * 2 * sizeof(double));
     L.gd = take(fld);
@@ -307,6 +309,8 @@ int stage_gamma_prep(const df_inst_t &p, const Shape &s, void *ws, size_t base, 
     a.gdm = at<double>(ws, base + L.gdm);
     a.pdm = at<double>(ws, base + L.pdm);
     a.gtr = at<double>(ws, base + L.gtr);
+    a.gp32 = at<float>(ws, base + L.gp32);
+    a.gtr32 = at<float>(ws, base + L.gtr32);
     HIPCHK(launch_gamma_prep(a, st));
     return DF_OK;
 }
@@ -404,6 +408,8 @@ int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &ac
             d.gdm = at<double>(ws, b + L.gdm);
             d.pdm = at<double>(ws, b + L.pdm);
             d.gtr = at<double>(ws, b + L.gtr);
+            d.gp32 = at<float>(ws, b + L.gp32);
+            d.gtr32 = at<float>(ws, b + L.gtr32);
             d.chi = inst[i].chi ? inst[i].chi : at<double>(ws, b + L.chi);
             d.w = inst[i].w ? inst[i].w : at<double>(ws, b + L.w);
             d.logdet = inst[i].logdet;
@@ -656,6 +662,8 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         a.gdm = at<double>(ws, b + L.gdm);
         a.pdm = at<double>(ws, b + L.pdm);
         a.gtr = at<double>(ws, b + L.gtr);
+        a.gp32 = at<float>(ws, b + L.gp32);
+        a.gtr32 = at<float>(ws, b + L.gtr32);
         a.chi = inst[i].chi;
         a.w = inst[i].w;
         a.logdet = inst[i].logdet;
@@ -952,6 +960,8 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         a.gdm = at<double>(ws, b + L.gdm);
         a.pdm = at<double>(ws, b + L.pdm);
         a.gtr = at<double>(ws, b + L.gtr);
+        a.gp32 = at<float>(ws, b + L.gp32);
+        a.gtr32 = at<float>(ws, b + L.gtr32);
         a.chi = chi;
         a.w = at<double>(ws, b + L.w);
         a.fallback_count = ints + kMaxClasses + i;

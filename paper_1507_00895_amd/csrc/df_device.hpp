@@ -74,6 +74,21 @@ __device__ __forceinline__ cd ld(const double *p, size_t i) {
 __device__ __forceinline__ void st(double *p, size_t i, cd v) {
     *(__attribute__((address_space(1))) dv2 *)(void *)(p + 2 * i) = dv2{v.re, v.im};
 }
+// FP32 pairs and quadruples (element i of an array of them)
+typedef float fv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ fv2 ld2f(const float *p, size_t i) {
+    return *(__attribute__((address_space(1))) const fv2 *)(const void *)(p + 2 * i);
+}
+__device__ __forceinline__ fv4 ld4f(const float *p, size_t i) {
+    return *(__attribute__((address_space(1))) const fv4 *)(const void *)(p + 4 * i);
+}
+__device__ __forceinline__ void st2f(float *p, size_t i, float a, float b) {
+    *(__attribute__((address_space(1))) fv2 *)(void *)(p + 2 * i) = fv2{a, b};
+}
+__device__ __forceinline__ void st4f(float *p, size_t i, float a, float b, float c, float d) {
+    *(__attribute__((address_space(1))) fv4 *)(void *)(p + 4 * i) = fv4{a, b, c, d};
+}
 
 // ----------------------------------------------------------------- k-grid
 // Flat index in C order over D axes of nk = 2^lognk points; every axis is a

@@ -244,6 +244,15 @@ __global__ __launch_bounds__(256) void k_gamma_prep(GammaPrepArgs a) {
             st(a.gtr, e, gdt);
             st(a.gtr, tot + e, gmt);
         }
+        if (a.gp32) {
+            const cd pd = gd * gdt, pmm = gm * gmt;
+            st4f(a.gp32, e, (float)gd.re, (float)gd.im, (float)pd.re, (float)pd.im);
+            st4f(a.gp32, tot + e, (float)gm.re, (float)gm.im, (float)pmm.re, (float)pmm.im);
+        }
+        if (a.gtr32) {
+            st2f(a.gtr32, e, (float)gdt.re, (float)gdt.im);
+            st2f(a.gtr32, tot + e, (float)gmt.re, (float)gmt.im);
+        }
     }
 }
 

@@ -76,11 +76,14 @@ struct GammaPrepArgs {
     double *gdm;                     // [2][n_om][n_nu][n_nu]
     double *pdm;                     // [2][n_om][n_nu][n_nu]
     double *gtr;                     // [2][n_om][n_nu][n_nu] (may be null)
+    float *gp32;                     // [2][n_om][n_nu][n_nu] (gamma, gamma_ij gamma_ji) in FP32, or null
+    float *gtr32;                    // [2][n_om][n_nu][n_nu] gamma transposed in FP32, or null
 };
 
 // One instance of a fused multi-instance ladder launch (device-side table).
 struct LadderInst {
     const double *gdm, *pdm, *gtr, *chi;
+    const float *gp32, *gtr32;
     double *w, *logdet;
     int8_t *status;
     int *count;                      // ladders outside the radius (atomic)
@@ -105,6 +108,8 @@ struct LadderArgs {
     const int *in_count;             // ... (count on the device) instead of item0 + block
     const LadderInst *insts;         // non-null: fused launch over n_insts instances,
     int n_insts;                     // items are global; the fields above are resolved per item
+    const float *gp32;               // FP32 ladder: (gamma, gamma_ij gamma_ji) pairs, FP32
+    const float *gtr32;              // FP32 ladder: gamma transposed, FP32
 };
 
 // Fused launches: find the instance of a global item, fill the per-instance
@@ -117,6 +122,8 @@ __device__ __forceinline__ int resolve_item(LadderArgs &a, int item) {
     a.gdm = d.gdm;
     a.pdm = d.pdm;
     a.gtr = d.gtr;
+    a.gp32 = d.gp32;
+    a.gtr32 = d.gtr32;
     a.chi = d.chi;
     a.w = d.w;
     a.logdet = d.logdet;

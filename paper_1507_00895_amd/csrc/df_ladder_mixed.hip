@@ -42,9 +42,10 @@ template <int NP> struct PlainShared {
     GjShared<float, NP> gj;
 };
 
-// REFINE = false: the FP32 ladder alone, Gamma_nn = sum_l X_nl gamma_ln with
-// X = D^-1 from the FP32 sweep (products and sums in FP64).  Relative error of
-// order kappa eps32, about 1e-6 for certified items.
+// REFINE = false: the FP32 ladder alone, from FP32 copies of the vertex
+// arrays: D, t and Gamma_nn = sum_l X_nl gamma_ln with X = D^-1 from the FP32
+// sweep, all in FP32.  Relative error of order kappa n eps32, about 1e-6 for
+// certified items.
 template <int NP, bool REFINE>
 __device__ __forceinline__ void mixed_body(LadderArgs a0) {
     constexpr int NT = NP / 16;
@@ -80,6 +81,37 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
     const int nm1 = n_nu - 1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
+    if constexpr (!REFINE) {
+        // FP32 ladder: vertex and gamma_ij gamma_ji as FP32 pairs, one load each
+        const float *gp = a.gp32 + 4 * (size_t)cm * nn;
+        cf tf[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tf[r] = {0.f, 0.f};
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc) {
+            const int j = 16 * tc + lj;
+            const cd xd = ld(chi, (size_t)min(j, nm1) * N + q);
+            const cf xj = {(float)xd.re, (float)xd.im};
+            fv4 gv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                gv[r] = ld4f(gp, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * w + MT<float>::row(lg, r);
+                const bool in = (i < n_nu) && (j < n_nu);
+                const cf x = cf{gv[r].x, gv[r].y} * xj;
+                Cr[tc][r] = ((i == j) ? 1.f : 0.f) - (in ? x.re : 0.f);
+                Ci[tc][r] = in ? -x.im : 0.f;
+                tf[r] = fma_c(tf[r], in ? cf{gv[r].z, gv[r].w} : cf{0.f, 0.f}, xj);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tp[r] = {(double)tf[r].re, (double)tf[r].im};
+    } else {
+    const int nm1 = n_nu - 1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) {
         const int j = 16 * tc + lj;
@@ -107,6 +139,7 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
                 tp[r] = fma_c(tp[r], in ? pv[k] : cd{0.0, 0.0}, xj);
             }
         }
+    }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) tp[r] = row16_sum(tp[r]);
@@ -143,27 +176,30 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             // per tile column without branches.  Opaque copies of the row and
             // column bases keep the compiler from sharing these indices with
             // those of the D build (which would hold them across the sweep).
-            const double *gtr = a.gtr + 2 * (size_t)cm * nn;
+            const float *gtr = a.gtr32 + 2 * (size_t)cm * nn;
             const int nm1 = n_nu - 1;
             int row0 = 16 * w, col0 = lj;
             asm volatile("" : "+v"(row0), "+v"(col0));
-            cd yp[4];
+            cf yf[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) yp[r] = {0.0, 0.0};
+            for (int r = 0; r < 4; ++r) yf[r] = {0.f, 0.f};
 #pragma unroll
             for (int tc = 0; tc < NT; ++tc) {
                 const int j = 16 * tc + col0;
-                cd gv[4];
+                fv2 gv[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    gv[r] = ld(gtr, (size_t)min(row0 + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+                    gv[r] = ld2f(gtr, (size_t)min(row0 + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const bool in = (row0 + MT<float>::row(lg, r) < n_nu) && (j < n_nu);
-                    yp[r] = fma_c(yp[r], cd{(double)Cr[tc][r], (double)Ci[tc][r]},
-                                  in ? gv[r] : cd{0.0, 0.0});
+                    yf[r] = fma_c(yf[r], cf{Cr[tc][r], Ci[tc][r]},
+                                  in ? cf{gv[r].x, gv[r].y} : cf{0.f, 0.f});
                 }
             }
+            cd yp[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) yp[r] = {(double)yf[r].re, (double)yf[r].im};
 #pragma unroll
             for (int r = 0; r < 4; ++r) yp[r] = row16_sum(yp[r]);
             if (lj == 0) {
