@@ -177,7 +177,8 @@ def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None, acce
 KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}>", "gjb_o3": "k_ladder_gjb_f64_o3<{np}>",
                  "vector": "k_ladder_fp64<{np},...>", "mfma": "k_ladder_mfma_f64<{np}>",
                  "mixed": "k_ladder_mixed<{np}>", "mixed_o3": "k_ladder_mixed_o3<{np}>",
-                 "fp32": "k_ladder_fp32<{np}>", "fp32_o4": "k_ladder_fp32_o4<{np}>"}
+                 "fp32": "k_ladder_fp32<{np}>", "fp32_o4": "k_ladder_fp32_o4<{np}>",
+                 "fp32_o5": "k_ladder_fp32_o5<{np}>"}
 
 
 def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
@@ -185,7 +186,7 @@ def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
     achieved = flops_launch / (lad_ms * 1e-3) / 1e12
     variant = B.df_ladder_variant(n_nu, prec)
     kernel_name = KERNEL_SYMBOL[variant].format(np=n_nu)
-    if variant in ("fp32", "fp32_o4"):
+    if variant in ("fp32", "fp32_o4", "fp32_o5"):
         peak = FP32_PEAK_TFLOPS
     elif variant not in ("mixed", "mixed_o3"):
         peak = FP64_PEAK_TFLOPS

@@ -243,6 +243,7 @@ int launch_ladder_variant(int v, LadderArgs a, int *queue, int *qcount, hipStrea
     switch (v) {
         case LV_FP32: HIPCHK(launch_ladder_fp32(a, 0, st)); break;
         case LV_FP32_O4: HIPCHK(launch_ladder_fp32(a, 4, st)); break;
+        case LV_FP32_O5: HIPCHK(launch_ladder_fp32(a, 5, st)); break;
         case LV_MIXED: HIPCHK(launch_ladder_mixed(a, 0, st)); break;
         case LV_MIXED_O3: HIPCHK(launch_ladder_mixed(a, 3, st)); break;
         case LV_GJB_O3: HIPCHK(launch_ladder_gjb_f64(a, 3, st)); break;

@@ -171,8 +171,8 @@ hipError_t launch_ladder_gjb_f64(const LadderArgs &a, int occ, hipStream_t s);
 int ladder_mixed_padded_size(int n_nu);
 bool ladder_mixed_has_occ3(int n_nu);
 hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, hipStream_t s);
-// FP32 only, no refinement (same sizes as the mixed kernel); occ = 4 selects the
-// build capped at four waves per SIMD
+// FP32 only, no refinement (same sizes as the mixed kernel); occ = 4 or 5
+// selects the build capped at that many waves per SIMD
 hipError_t launch_ladder_fp32(const LadderArgs &a, int occ, hipStream_t s);
 // pivoting kernel over a device-side queue of items (grid-stride, fixed grid)
 hipError_t launch_ladder_fp64_queue(const LadderArgs &a, int blocks, hipStream_t s);

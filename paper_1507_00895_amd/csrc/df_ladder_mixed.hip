@@ -353,6 +353,11 @@ __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ladder_fp32_o4(LadderArgs a0) {
     mixed_body<NP, false>(a0);
 }
+template <int NP>
+__global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(5, 5)))
+void k_ladder_fp32_o5(LadderArgs a0) {
+    mixed_body<NP, false>(a0);
+}
 
 template <int NP>
 static hipError_t launch_mixed(const LadderArgs &a, int occ, hipStream_t s) {
@@ -368,7 +373,9 @@ static hipError_t launch_mixed(const LadderArgs &a, int occ, hipStream_t s) {
 
 template <int NP>
 static hipError_t launch_fp32(const LadderArgs &a, int occ, hipStream_t s) {
-    if (occ == 4)
+    if (occ == 5)
+        hipLaunchKernelGGL((k_ladder_fp32_o5<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+    else if (occ == 4)
         hipLaunchKernelGGL((k_ladder_fp32_o4<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
     else
         hipLaunchKernelGGL((k_ladder_fp32<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);

@@ -18,7 +18,8 @@ enum LadderVariant {
     LV_MIXED_O3 = 5,   // same, capped for three waves per SIMD
     LV_FP32 = 6,       // certified FP32 sweep alone
     LV_FP32_O4 = 7,    // same, capped for four waves per SIMD
-    LV_COUNT = 8
+    LV_FP32_O5 = 8,    // same, capped for five waves per SIMD
+    LV_COUNT = 9
 };
 
 const char *variant_name(int v);
