@@ -79,9 +79,9 @@ def parse():
                     help="skip the seconds-per-converged-Sigma~ legs of all paths")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-started path")
     ap.add_argument("--no-tune", action="store_true", help="keep the default ladder kernels")
-    ap.add_argument("--warm-train", type=int, default=96,
+    ap.add_argument("--warm-train", type=int, default=128,
                     help="converged instances the warm-start network is trained on")
-    ap.add_argument("--warm-steps", type=int, default=4000)
+    ap.add_argument("--warm-steps", type=int, default=6000)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
