@@ -175,6 +175,7 @@ def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None, acce
 
 
 KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}>", "gjb_o3": "k_ladder_gjb_f64_o3<{np}>",
+                 "gjb_o4": "k_ladder_gjb_f64_o4<{np}>",
                  "vector": "k_ladder_fp64<{np},...>", "mfma": "k_ladder_mfma_f64<{np}>",
                  "mixed": "k_ladder_mixed<{np}>", "mixed_o3": "k_ladder_mixed_o3<{np}>",
                  "fp32": "k_ladder_fp32<{np}>", "fp32_o4": "k_ladder_fp32_o4<{np}>",

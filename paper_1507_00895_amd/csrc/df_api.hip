@@ -247,6 +247,7 @@ int launch_ladder_variant(int v, LadderArgs a, int *queue, int *qcount, hipStrea
         case LV_MIXED: HIPCHK(launch_ladder_mixed(a, 0, st)); break;
         case LV_MIXED_O3: HIPCHK(launch_ladder_mixed(a, 3, st)); break;
         case LV_GJB_O3: HIPCHK(launch_ladder_gjb_f64(a, 3, st)); break;
+        case LV_GJB_O4: HIPCHK(launch_ladder_gjb_f64(a, 4, st)); break;
         default: HIPCHK(launch_ladder_gjb_f64(a, 0, st)); break;
     }
     LadderArgs b = a;

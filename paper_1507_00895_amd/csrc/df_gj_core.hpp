@@ -183,9 +183,10 @@ __device__ __forceinline__ double wave_max_pos(double x) {
 }
 
 // ---------------------------------------------------------------- shared state
+// The inverted diagonal tile of step t is published in Xw[t]: the wave that
+// inverts it has no layout exchange of its own at that step.
 template <typename T, int NP> struct GjShared {
     static constexpr int NT = NP / 16;
-    cplx<T> Tt[16][17];          // diagonal tile, then its inverse
     cplx<T> Rb[16][NP];          // old block-row of the current tile column
     cplx<T> Xw[NT][16][17];      // per-wave layout exchange (accumulator -> operand)
     cd pivv[NP];                 // scalar pivots, FP64
@@ -363,7 +364,7 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
             gj_tile_invert<T>(Xr, Xi, &pvl);
             if (l < 16) sh.pivv[16 * t + l] = pvl;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sh.Tt[MT<T>::row(lg, r)][lj] = ct{Xr[r], Xi[r]};
+            for (int r = 0; r < 4; ++r) sh.Xw[t][MT<T>::row(lg, r)][lj] = ct{Xr[r], Xi[r]};
         } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Cr[0][r], Ci[0][r]};
@@ -374,7 +375,7 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
         if (w == t) {
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
-                ct g = sh.Tt[lj][4 * k4 + lg];
+                ct g = sh.Xw[t][lj][4 * k4 + lg];
                 if (lj == 4 * k4 + lg) g.re -= T(1);
                 gr[k4] = g.re;
                 gim[k4] = g.im;
@@ -385,7 +386,7 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
                 const ct xa = sh.Xw[w][lj][4 * k4 + lg];
-                const ct b = sh.Tt[4 * k4 + lg][lj];
+                const ct b = sh.Xw[t][4 * k4 + lg][lj];
                 const T nxr = -xa.re, nxi = -xa.im;
                 Gr = MT<T>::mma(nxr, b.re, Gr);
                 Gr = MT<T>::mma(xa.im, b.im, Gr);

@@ -149,6 +149,7 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
 
 // Two register budgets of the same kernel: the compiler's own (two
 // work-groups per CU at NP = 48, 64) and one capped for three waves per SIMD.
+// A build capped for four waves (it spills) is a further tuner candidate.
 // (At NP = 96 the capped build spills and measured 25 % slower: not built.)
 template <int NP>
 __global__ __launch_bounds__(NP * 4) void k_ladder_gjb_f64(LadderArgs a0) {
@@ -159,12 +160,21 @@ __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(3, 3)))
 void k_ladder_gjb_f64_o3(LadderArgs a0) {
     gjb_body<NP>(a0);
 }
+template <int NP>
+__global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_ladder_gjb_f64_o4(LadderArgs a0) {
+    gjb_body<NP>(a0);
+}
 
 template <int NP>
 static hipError_t launch_gjb(const LadderArgs &a, int occ, hipStream_t s) {
     if constexpr (NP <= 64) {
         if (occ == 3) {
             hipLaunchKernelGGL((k_ladder_gjb_f64_o3<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+            return hipGetLastError();
+        }
+        if (occ == 4) {
+            hipLaunchKernelGGL((k_ladder_gjb_f64_o4<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
             return hipGetLastError();
         }
     }
@@ -189,7 +199,7 @@ bool ladder_gjb_has_occ3(int n_nu) {
 }
 
 hipError_t launch_ladder_gjb_f64(const LadderArgs &a, int occ, hipStream_t s) {
-    if (occ == 3 && !ladder_gjb_has_occ3(a.n_nu)) return hipErrorInvalidValue;
+    if ((occ == 3 || occ == 4) && !ladder_gjb_has_occ3(a.n_nu)) return hipErrorInvalidValue;
     switch (ladder_gjb_padded_size(a.n_nu)) {
         case 16: return launch_gjb<16>(a, occ, s);
         case 32: return launch_gjb<32>(a, occ, s);

@@ -16,7 +16,7 @@ namespace df {
 namespace {
 
 const char *const kNames[LV_COUNT] = {"gjb",   "gjb_o3",   "vector",  "mfma",   "mixed",
-                                     "mixed_o3", "fp32", "fp32_o4", "fp32_o5"};
+                                     "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4"};
 
 std::mutex g_mu;
 std::map<std::pair<int, int>, int> g_table;
@@ -58,7 +58,8 @@ int variant_from_name(const char *name) {
 int variant_padded_size(int v, int n_nu) {
     switch (v) {
         case LV_GJB: return ladder_gjb_padded_size(n_nu);
-        case LV_GJB_O3: return ladder_gjb_has_occ3(n_nu) ? ladder_gjb_padded_size(n_nu) : 0;
+        case LV_GJB_O3:
+        case LV_GJB_O4: return ladder_gjb_has_occ3(n_nu) ? ladder_gjb_padded_size(n_nu) : 0;
         case LV_VECTOR: return ladder_padded_size(n_nu);
         case LV_MFMA: return ladder_mfma_padded_size(n_nu);
         case LV_MIXED: return ladder_mixed_padded_size(n_nu);

@@ -19,7 +19,8 @@ enum LadderVariant {
     LV_FP32 = 6,       // certified FP32 sweep alone
     LV_FP32_O4 = 7,    // same, capped for four waves per SIMD
     LV_FP32_O5 = 8,    // same, capped for five waves per SIMD
-    LV_COUNT = 9
+    LV_GJB_O4 = 9,     // certified FP64 kernel capped for four waves per SIMD (spills)
+    LV_COUNT = 10
 };
 
 const char *variant_name(int v);
