@@ -38,6 +38,11 @@ template <> struct MT<double> {
     static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    // c - a b: on the FP64 matrix instruction the last field negates the A
+    // operand (bit 0), so no register holds -a
+    static __device__ __forceinline__ v4 mma_na(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 1);
+    }
     static __device__ __forceinline__ int row(int lg, int r) { return lg + 4 * r; }
     // row s of a tile sits in row group lg_of(s), register r_of(s)
     static __device__ __forceinline__ int lg_of(int s) { return s & 3; }
@@ -47,6 +52,10 @@ template <> struct MT<float> {
     typedef float v4 __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // c - a b (the FP32 instruction's last field is a broadcast control)
+    static __device__ __forceinline__ v4 mma_na(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(-a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int lg, int r) { return 4 * lg + r; }
     static __device__ __forceinline__ int lg_of(int s) { return s >> 2; }
@@ -371,7 +380,7 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
         }
         __syncthreads();
 
-        T gr[4], gim[4], gn[4];
+        T gr[4], gim[4];
         if (w == t) {
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
@@ -379,7 +388,6 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
                 if (lj == 4 * k4 + lg) g.re -= T(1);
                 gr[k4] = g.re;
                 gim[k4] = g.im;
-                gn[k4] = -g.im;
             }
         } else {
             v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};
@@ -387,11 +395,10 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
             for (int k4 = 0; k4 < 4; ++k4) {
                 const ct xa = sh.Xw[w][lj][4 * k4 + lg];
                 const ct b = sh.Xw[t][4 * k4 + lg][lj];
-                const T nxr = -xa.re, nxi = -xa.im;
-                Gr = MT<T>::mma(nxr, b.re, Gr);
+                Gr = MT<T>::mma_na(xa.re, b.re, Gr);
                 Gr = MT<T>::mma(xa.im, b.im, Gr);
-                Gi = MT<T>::mma(nxr, b.im, Gi);
-                Gi = MT<T>::mma(nxi, b.re, Gi);
+                Gi = MT<T>::mma_na(xa.re, b.im, Gi);
+                Gi = MT<T>::mma_na(xa.im, b.re, Gi);
             }
             Cr[0] = Gr;
             Ci[0] = Gi;
@@ -404,7 +411,6 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
                 const ct g = sh.Xw[w][lj][4 * k4 + lg];
                 gr[k4] = g.re;
                 gim[k4] = g.im;
-                gn[k4] = -g.im;
             }
         }
 #pragma unroll
@@ -414,7 +420,7 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
             for (int k4 = 0; k4 < 4; ++k4) {
                 const ct b = sh.Rb[4 * k4 + lg][16 * c + lj];
                 Cr[p] = MT<T>::mma(gr[k4], b.re, Cr[p]);
-                Cr[p] = MT<T>::mma(gn[k4], b.im, Cr[p]);
+                Cr[p] = MT<T>::mma_na(gim[k4], b.im, Cr[p]);
                 Ci[p] = MT<T>::mma(gr[k4], b.im, Ci[p]);
                 Ci[p] = MT<T>::mma(gim[k4], b.re, Ci[p]);
             }

@@ -285,14 +285,13 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
                 const int ia = 16 * w + lj;
                 const cd ga = (ia < n_nu && 16 * kt + 4 * k4 + lg < n_nu)
                                   ? ld(gam, (size_t)ia * n_nu + k) : cd{0.0, 0.0};
-                const double ngi = -ga.im;
                 const cd xk = (k < n_nu) ? ld(chi, (size_t)k * N + q) : cd{0.0, 0.0};
 #pragma unroll
                 for (int tc = 0; tc < NT; ++tc) {
                     const cf z = sh.ref.Zs[k][16 * tc + lj];
                     const cd b = xk * cd{(double)z.re, (double)z.im};
                     Er[tc] = MT<double>::mma(ga.re, b.re, Er[tc]);
-                    Er[tc] = MT<double>::mma(ngi, b.im, Er[tc]);
+                    Er[tc] = MT<double>::mma_na(ga.im, b.im, Er[tc]);
                     Ei[tc] = MT<double>::mma(ga.re, b.im, Ei[tc]);
                     Ei[tc] = MT<double>::mma(ga.im, b.re, Ei[tc]);
                 }
