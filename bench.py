@@ -178,6 +178,7 @@ KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}>", "gjb_o3": "k_ladder_gjb_f64_o3
                  "gjb_o4": "k_ladder_gjb_f64_o4<{np}>",
                  "vector": "k_ladder_fp64<{np},...>", "mfma": "k_ladder_mfma_f64<{np}>",
                  "mixed": "k_ladder_mixed<{np}>", "mixed_o3": "k_ladder_mixed_o3<{np}>",
+                 "mixed_o4": "k_ladder_mixed_o4<{np}>",
                  "fp32": "k_ladder_fp32<{np}>", "fp32_o4": "k_ladder_fp32_o4<{np}>",
                  "fp32_o5": "k_ladder_fp32_o5<{np}>"}
 
@@ -188,7 +189,7 @@ def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
     kernel_name = KERNEL_SYMBOL[variant].format(np=n_nu)
     if variant in ("fp32", "fp32_o4", "fp32_o5"):
         peak = FP32_PEAK_TFLOPS
-    elif variant not in ("mixed", "mixed_o3"):
+    elif variant not in ("mixed", "mixed_o3", "mixed_o4"):
         peak = FP64_PEAK_TFLOPS
     else:
         # The refined solve's own work per solve: the inverse and Z0 = X gamma in

@@ -189,7 +189,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
                 size_t ws_bytes, df_stream_t stream);
 
 /* Name of the ladder kernel variant that calls for this n_nu and precision use
- * now ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4"),
+ * now ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4", "mixed_o4"),
  * for prec DF_FP64, DF_FP32_REFINE or DF_FP32, written to the
  * host buffer name (NUL-terminated, name_len bytes at most). */
 int df_ladder_variant(int32_t n_nu, int32_t prec, char *name, size_t name_len);

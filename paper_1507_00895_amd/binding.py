@@ -279,7 +279,7 @@ def df_ladder_set_variant(n_nu: int, prec: int, name: str):
                                                                         name.encode()))
 
 
-LADDER_VARIANTS = ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4")
+LADDER_VARIANTS = ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4", "mixed_o4")
 
 
 def df_autotune_reset():

@@ -195,11 +195,12 @@ int ensure_attrs() {
 }
 
 // ---- ladder kernel choice ---------------------------------------------------
-// In order: the variant named by DF_LADDER_KERNEL (gjb, gjb_o3, vector, mfma,
-// mixed, mixed_o3) when it serves this n_nu and precision; the autotuner's
-// choice; the default, which is the certified pivot-free blocked kernel on the
-// matrix cores (FP64, or FP32 + FP64 refinement), whose uncertified items go
-// to the partial-pivoting kernel.
+// In order: the variant named by DF_LADDER_KERNEL (any name of the variant
+// table) when it serves this n_nu and precision; the autotuner's choice; the
+// default, which is the certified pivot-free blocked kernel on the matrix cores
+// (FP64, FP32 + FP64 refinement, or FP32), in its three-wave build where there
+// is one (four waves for FP32), whose uncertified items go to the
+// partial-pivoting kernel.
 int env_variant() {
     static int v = -2;
     if (v == -2) {
@@ -210,8 +211,9 @@ int env_variant() {
 }
 
 int default_variant(int n_nu, int prec) {
-    if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(n_nu) != 0) return LV_MIXED;
-    if (prec == DF_FP32 && ladder_mixed_padded_size(n_nu) != 0) return LV_FP32;
+    if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(n_nu) != 0) return LV_MIXED_O3;
+    if (prec == DF_FP32 && ladder_mixed_padded_size(n_nu) != 0) return LV_FP32_O4;
+    if (ladder_gjb_has_occ3(n_nu)) return LV_GJB_O3;
     if (ladder_gjb_padded_size(n_nu) != 0) return LV_GJB;
     return LV_VECTOR;
 }
@@ -246,6 +248,7 @@ int launch_ladder_variant(int v, LadderArgs a, int *queue, int *qcount, hipStrea
         case LV_FP32_O5: HIPCHK(launch_ladder_fp32(a, 5, st)); break;
         case LV_MIXED: HIPCHK(launch_ladder_mixed(a, 0, st)); break;
         case LV_MIXED_O3: HIPCHK(launch_ladder_mixed(a, 3, st)); break;
+        case LV_MIXED_O4: HIPCHK(launch_ladder_mixed(a, 4, st)); break;
         case LV_GJB_O3: HIPCHK(launch_ladder_gjb_f64(a, 3, st)); break;
         case LV_GJB_O4: HIPCHK(launch_ladder_gjb_f64(a, 4, st)); break;
         default: HIPCHK(launch_ladder_gjb_f64(a, 0, st)); break;

@@ -31,12 +31,17 @@ constexpr double CERT_MAX_MIXED = 0.99;
 template <int NP> struct MixedShared {
     union {
         GjShared<float, NP> gj;          // during the FP32 sweep
-        struct {
-            cf Xs[NP][NP];               // X = D^-1 (FP32), all rows
-            cf Zs[NP][NP];               // Z0 = X gamma (FP32), all rows
-        } ref;                           // during the refinement
+        cf Tw[NP / 16][16][17];          // Z0 = X gamma: per-wave exchange of X tiles
+        cf Zs[NP][NP];                   // then Z0 (FP32), all rows; later E
     };
 };
+// Column slot of element (i, j) in Zs: odd rows swap the 16-column halves
+// of each 32-column block (NP a multiple of 32), so that the two rows read
+// by one half-wave fall in different LDS banks.
+template <int NP> __device__ __forceinline__ int zs_col(int i, int j) {
+    if constexpr (NP % 32 == 0) return j ^ ((i & 1) << 4);
+    else return j;
+}
 // Without refinement only the sweep's state is needed.
 template <int NP> struct PlainShared {
     GjShared<float, NP> gj;
@@ -52,7 +57,7 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
     typedef MT<float>::v4 f4;
     typedef MT<double>::v4 d4;
     __shared__ typename std::conditional<REFINE, MixedShared<NP>, PlainShared<NP>>::type sh;
-    __shared__ cd ypart[NT][NP];
+    __shared__ cd ypart[NP];
     __shared__ cd tv[NP];
     __shared__ int s_flag;
 
@@ -114,7 +119,8 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
     for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) {
-        const int j = 16 * tc + lj;
+        int j = 16 * tc + lj;
+        asm volatile("" : "+v"(j));   // keeps each tile column's loads in place
         const cd xj = ld(chi, (size_t)min(j, nm1) * N + q);
         // two rows per batch of loads: the FP32 kernels run on a tighter
         // register budget
@@ -204,7 +210,7 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             for (int r = 0; r < 4; ++r) yp[r] = row16_sum(yp[r]);
             if (lj == 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) ypart[0][16 * w + MT<float>::row(lg, r)] = yp[r];
+                for (int r = 0; r < 4; ++r) ypart[16 * w + MT<float>::row(lg, r)] = yp[r];
             }
         }
         __syncthreads();
@@ -212,7 +218,7 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             const cd tt = tv[n];
             cd wv;
             if (stt == 0) {
-                const cd y = ypart[0][n];
+                const cd y = ypart[n];
                 wv = {y.re - 0.5 * tt.re, y.im - 0.5 * tt.im};
             } else {
                 const cd gnn = ld(gam, (size_t)n * n_nu + n);
@@ -221,16 +227,14 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             st(a.w, ((size_t)cm * n_nu + n) * N + q, wv);
         }
     } else {
+    // Refinement on this wave's block-row.  The FP32 accumulator layout puts
+    // row 4 lg + r of a tile in lane group lg, register r; the FP64 products
+    // below feed their A-operand rows in the order perm(i) = 4 (i & 3) + (i >> 2),
+    // so that their output sits in the same lanes and registers as the FP32 one.
     if (stt == 0) {
-        // ---- share X (all waves' block-rows)
-#pragma unroll
-        for (int tc = 0; tc < NT; ++tc)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                sh.ref.Xs[16 * w + MT<float>::row(lg, r)][16 * tc + lj] = cf{Cr[tc][r], Ci[tc][r]};
-        __syncthreads();
-
-        // ---- Z0 = X gamma on the FP32 matrix cores (block-row w)
+        const float *gp = a.gp32 + 4 * (size_t)cm * nn;   // (gamma, gamma_ij gamma_ji) in FP32
+        // ---- Z0 = X gamma on the FP32 matrix cores; the wave's X tiles reach the
+        // operand layout through its own LDS slot
         f4 Zr[NT], Zi[NT];
 #pragma unroll
         for (int tc = 0; tc < NT; ++tc) {
@@ -240,80 +244,126 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
 #pragma unroll
         for (int kt = 0; kt < NT; ++kt) {
 #pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sh.Tw[w][MT<float>::row(lg, r)][lj] = cf{Cr[kt][r], Ci[kt][r]};
+            wave_sync_lds();
+#pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
-                const int k = 16 * kt + 4 * k4 + lg;
-                const cf xa = sh.ref.Xs[16 * w + lj][k];
-                const float nxi = -xa.im;
+                // an opaque row index keeps these loads inside their step: hoisted,
+                // all NT x 16 of them would be live at once
+                int k = 16 * kt + 4 * k4 + lg;
+                asm volatile("" : "+v"(k));
+                const cf xa = sh.Tw[w][lj][4 * k4 + lg];
+                fv4 gv[NT];
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc)
+                    gv[tc] = ld4f(gp, (size_t)min(k, nm1) * n_nu + min(16 * tc + lj, nm1));
 #pragma unroll
                 for (int tc = 0; tc < NT; ++tc) {
-                    const int j = 16 * tc + lj;
-                    const cd g = (k < n_nu && j < n_nu) ? ld(gam, (size_t)k * n_nu + j) : cd{0.0, 0.0};
-                    const float br = (float)g.re, bi = (float)g.im;
+                    const bool in = (k < n_nu) && (16 * tc + lj < n_nu);
+                    const float br = in ? gv[tc].x : 0.f, bi = in ? gv[tc].y : 0.f;
                     Zr[tc] = MT<float>::mma(xa.re, br, Zr[tc]);
-                    Zr[tc] = MT<float>::mma(nxi, bi, Zr[tc]);
+                    Zr[tc] = MT<float>::mma_na(xa.im, bi, Zr[tc]);
                     Zi[tc] = MT<float>::mma(xa.re, bi, Zi[tc]);
                     Zi[tc] = MT<float>::mma(xa.im, br, Zi[tc]);
                 }
             }
+            wave_sync_lds();   // the slot is rewritten by the next tile
         }
+        __syncthreads();   // Zs overlays the exchange slots
+        // ---- share Z0 (the registers are free again once it is in LDS)
 #pragma unroll
         for (int tc = 0; tc < NT; ++tc)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                sh.ref.Zs[16 * w + MT<float>::row(lg, r)][16 * tc + lj] = cf{Zr[tc][r], Zi[tc][r]};
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * w + MT<float>::row(lg, r);
+                sh.Zs[i][zs_col<NP>(i, 16 * tc + lj)] = cf{Zr[tc][r], Zi[tc][r]};
+            }
         __syncthreads();
-
-        // ---- E = gamma - Z0 + gamma (chi Z0) on the FP64 matrix cores (block-row w)
+        // ---- E = gamma - Z0 on the wave's rows
         d4 Er[NT], Ei[NT];
 #pragma unroll
         for (int tc = 0; tc < NT; ++tc) {
-            const int j = 16 * tc + lj;
+            int j = 16 * tc + lj;
+            asm volatile("" : "+v"(j));
+            cd gv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                gv[r] = ld(gam, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = 16 * w + MT<double>::row(lg, r);
-                const cd g = (i < n_nu && j < n_nu) ? ld(gam, (size_t)i * n_nu + j) : cd{0.0, 0.0};
-                const cf z = sh.ref.Zs[i][j];
-                Er[tc][r] = g.re - (double)z.re;
-                Ei[tc][r] = g.im - (double)z.im;
-            }
-        }
-#pragma unroll
-        for (int kt = 0; kt < NT; ++kt) {
-#pragma unroll
-            for (int k4 = 0; k4 < 4; ++k4) {
-                const int k = 16 * kt + 4 * k4 + lg;
-                const int ia = 16 * w + lj;
-                const cd ga = (ia < n_nu && 16 * kt + 4 * k4 + lg < n_nu)
-                                  ? ld(gam, (size_t)ia * n_nu + k) : cd{0.0, 0.0};
-                const cd xk = (k < n_nu) ? ld(chi, (size_t)k * N + q) : cd{0.0, 0.0};
-#pragma unroll
-                for (int tc = 0; tc < NT; ++tc) {
-                    const cf z = sh.ref.Zs[k][16 * tc + lj];
-                    const cd b = xk * cd{(double)z.re, (double)z.im};
-                    Er[tc] = MT<double>::mma(ga.re, b.re, Er[tc]);
-                    Er[tc] = MT<double>::mma_na(ga.im, b.im, Er[tc]);
-                    Ei[tc] = MT<double>::mma(ga.re, b.im, Ei[tc]);
-                    Ei[tc] = MT<double>::mma(ga.im, b.re, Ei[tc]);
-                }
+                const int i = 16 * w + MT<float>::row(lg, r);
+                const bool in = (i < n_nu) && (j < n_nu);
+                const cf z = sh.Zs[i][zs_col<NP>(i, j)];
+                Er[tc][r] = (in ? gv[r].re : 0.0) - (double)z.re;
+                Ei[tc][r] = (in ? gv[r].im : 0.0) - (double)z.im;
             }
         }
 
-        // ---- (X E)_nn: this wave's rows k of E against X[n][k]
+        // ---- E += gamma (chi Z0) on the FP64 matrix cores
+        {
+            const int lp = 4 * (lj & 3) + (lj >> 2);   // perm(lj)
+            const int ia = 16 * w + lp;
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) {
-            const int n = 16 * tc + lj;
-            cd acc = {0.0, 0.0};
+            for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    int k = 16 * kt + 4 * k4 + lg;
+                    asm volatile("" : "+v"(k));
+                    const cd g0 = ld(gam, (size_t)min(ia, nm1) * n_nu + min(k, nm1));
+                    const cd xk = ld(chi, (size_t)min(k, nm1) * N + q);
+                    const bool in = (ia < n_nu) && (k < n_nu);
+                    const cd ga = in ? g0 : cd{0.0, 0.0};
+#pragma unroll
+                    for (int tc = 0; tc < NT; ++tc) {
+                        const cf z = sh.Zs[k][zs_col<NP>(k, 16 * tc + lj)];
+                        const cd b = xk * cd{(double)z.re, (double)z.im};
+                        Er[tc] = MT<double>::mma(ga.re, b.re, Er[tc]);
+                        Er[tc] = MT<double>::mma_na(ga.im, b.im, Er[tc]);
+                        Ei[tc] = MT<double>::mma(ga.re, b.im, Ei[tc]);
+                        Ei[tc] = MT<double>::mma(ga.im, b.re, Ei[tc]);
+                    }
+                }
+            }
+        }
+        // the diagonal of Z0 on this wave's rows, before E replaces Z0
+        cd zd[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * w + MT<float>::row(lg, r);
+            const cf z = sh.Zs[n][zs_col<NP>(n, n)];
+            zd[r] = {(double)z.re, (double)z.im};
+        }
+        __syncthreads();
+        // ---- E to LDS in FP32: E is of order kappa eps32 |gamma|, so its own
+        // FP32 rounding adds about 6e-8 of that to Gamma
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int k = 16 * w + MT<double>::row(lg, r);
-                const cf x = sh.ref.Xs[n][k];
-                acc = fma_c(acc, cd{(double)x.re, (double)x.im}, cd{Er[tc][r], Ei[tc][r]});
+                const int i = 16 * w + MT<float>::row(lg, r);
+                sh.Zs[i][zs_col<NP>(i, 16 * tc + lj)] = cf{(float)Er[tc][r], (float)Ei[tc][r]};
             }
-            acc.re += __shfl_xor(acc.re, 16, 64);
-            acc.im += __shfl_xor(acc.im, 16, 64);
-            acc.re += __shfl_xor(acc.re, 32, 64);
-            acc.im += __shfl_xor(acc.im, 32, 64);
-            if (lg == 0) ypart[w][n] = acc;
+        __syncthreads();
+        // ---- (X E)_nn for the wave's rows n: lane lj takes k = 16 tc + lj
+        cd acc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = {0.0, 0.0};
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * w + MT<float>::row(lg, r);
+                const int k = 16 * tc + lj;
+                const cf e = sh.Zs[k][zs_col<NP>(k, n)];
+                acc[r] = fma_c(acc[r], cd{(double)Cr[tc][r], (double)Ci[tc][r]},
+                               cd{(double)e.re, (double)e.im});
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = row16_sum(acc[r]);
+        if (lj == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ypart[16 * w + MT<float>::row(lg, r)] = zd[r] + acc[r];
         }
     }
     __syncthreads();
@@ -321,9 +371,7 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
         const cd tt = tv[n];
         cd wv;
         if (stt == 0) {
-            const cf z = sh.ref.Zs[n][n];
-            cd y = {(double)z.re, (double)z.im};
-            for (int x = 0; x < NT; ++x) y = y + ypart[x][n];
+            const cd y = ypart[n];
             wv = {y.re - 0.5 * tt.re, y.im - 0.5 * tt.im};
         } else {
             const cd gnn = ld(gam, (size_t)n * n_nu + n);
@@ -344,6 +392,11 @@ void k_ladder_mixed_o3(LadderArgs a0) {
     mixed_body<NP, true>(a0);
 }
 template <int NP>
+__global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_ladder_mixed_o4(LadderArgs a0) {
+    mixed_body<NP, true>(a0);
+}
+template <int NP>
 __global__ __launch_bounds__(NP * 4) void k_ladder_fp32(LadderArgs a0) {
     mixed_body<NP, false>(a0);
 }
@@ -360,11 +413,13 @@ void k_ladder_fp32_o5(LadderArgs a0) {
 
 template <int NP>
 static hipError_t launch_mixed(const LadderArgs &a, int occ, hipStream_t s) {
-    if constexpr (NP <= 48) {
-        if (occ == 3) {
-            hipLaunchKernelGGL((k_ladder_mixed_o3<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
-            return hipGetLastError();
-        }
+    if (occ == 3) {
+        hipLaunchKernelGGL((k_ladder_mixed_o3<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+        return hipGetLastError();
+    }
+    if (occ == 4) {
+        hipLaunchKernelGGL((k_ladder_mixed_o4<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL((k_ladder_mixed<NP>), dim3(a.n_items), dim3(NP * 4), 0, s, a);
     return hipGetLastError();
@@ -387,22 +442,21 @@ int ladder_mixed_padded_size(int n_nu) {
     if (n_nu <= 32) return 32;
     if (n_nu <= 48) return 48;
     if (n_nu <= 64) return 64;
-    return 0;   // the FP32 X and Z0 of larger matrices exceed the LDS budget
+    return 0;   // larger sizes take the FP64 kernels
 }
 
-// three work-groups per CU fit the LDS only up to NP = 48
+// three and four work-groups per CU fit the LDS at every size (34 KB at NP = 64)
 bool ladder_mixed_has_occ3(int n_nu) {
-    const int np = ladder_mixed_padded_size(n_nu);
-    return np != 0 && np <= 48;
+    return ladder_mixed_padded_size(n_nu) != 0;
 }
 
 hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, hipStream_t s) {
-    if (occ == 3 && !ladder_mixed_has_occ3(a.n_nu)) return hipErrorInvalidValue;
+    if ((occ == 3 || occ == 4) && !ladder_mixed_has_occ3(a.n_nu)) return hipErrorInvalidValue;
     switch (ladder_mixed_padded_size(a.n_nu)) {
         case 16: return launch_mixed<16>(a, occ, s);
         case 32: return launch_mixed<32>(a, occ, s);
         case 48: return launch_mixed<48>(a, occ, s);
-        case 64: return launch_mixed<64>(a, 0, s);
+        case 64: return launch_mixed<64>(a, occ, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -16,7 +16,8 @@ namespace df {
 namespace {
 
 const char *const kNames[LV_COUNT] = {"gjb",   "gjb_o3",   "vector",  "mfma",   "mixed",
-                                     "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4"};
+                                     "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4",
+                                     "mixed_o4"};
 
 std::mutex g_mu;
 std::map<std::pair<int, int>, int> g_table;
@@ -63,7 +64,8 @@ int variant_padded_size(int v, int n_nu) {
         case LV_VECTOR: return ladder_padded_size(n_nu);
         case LV_MFMA: return ladder_mfma_padded_size(n_nu);
         case LV_MIXED: return ladder_mixed_padded_size(n_nu);
-        case LV_MIXED_O3: return ladder_mixed_has_occ3(n_nu) ? ladder_mixed_padded_size(n_nu) : 0;
+        case LV_MIXED_O3:
+        case LV_MIXED_O4: return ladder_mixed_has_occ3(n_nu) ? ladder_mixed_padded_size(n_nu) : 0;
         case LV_FP32:
         case LV_FP32_O4:
         case LV_FP32_O5: return ladder_mixed_padded_size(n_nu);
@@ -74,7 +76,8 @@ int variant_padded_size(int v, int n_nu) {
 int variant_prec(int v) {
     switch (v) {
         case LV_MIXED:
-        case LV_MIXED_O3: return DF_FP32_REFINE;
+        case LV_MIXED_O3:
+        case LV_MIXED_O4: return DF_FP32_REFINE;
         case LV_FP32:
         case LV_FP32_O4:
         case LV_FP32_O5: return DF_FP32;

@@ -20,7 +20,8 @@ enum LadderVariant {
     LV_FP32_O4 = 7,    // same, capped for four waves per SIMD
     LV_FP32_O5 = 8,    // same, capped for five waves per SIMD
     LV_GJB_O4 = 9,     // certified FP64 kernel capped for four waves per SIMD (spills)
-    LV_COUNT = 10
+    LV_MIXED_O4 = 10,  // FP32 + FP64 refinement capped for four waves per SIMD (spills)
+    LV_COUNT = 11
 };
 
 const char *variant_name(int v);

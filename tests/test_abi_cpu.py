@@ -154,19 +154,21 @@ def test_mlp_host_validation():
 
 def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     B.df_autotune_reset()
-    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb"
-    assert B.df_ladder_variant(64, B.DF_FP32_REFINE) == "mixed"
+    # defaults: the capped builds that measured fastest at n_nu = 64
+    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3"
+    assert B.df_ladder_variant(64, B.DF_FP32_REFINE) == "mixed_o3"
     assert B.df_ladder_variant(96, B.DF_FP32_REFINE) == "gjb"      # beyond the mixed kernel
     assert B.df_ladder_variant(128, B.DF_FP64) == "gjb"
-    assert B.df_ladder_variant(64, B.DF_FP32) == "fp32"
+    assert B.df_ladder_variant(64, B.DF_FP32) == "fp32_o4"
     assert B.df_ladder_variant(128, B.DF_FP32) == "gjb"
     with pytest.raises(B.DfError):
         B.df_ladder_variant(64, B.DF_ADAPTIVE)
-    B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o3")
-    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3"
-    assert B.df_ladder_variant(62, B.DF_FP64) == "gjb"               # keyed by exact n_nu
-    for bad in [(96, B.DF_FP64, "gjb_o3"), (128, B.DF_FP64, "gjb_o3"), (64, B.DF_FP64, "mixed"),
-                (64, B.DF_FP32_REFINE, "vector"), (64, B.DF_FP32_REFINE, "mixed_o3"),
+    B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o4")
+    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o4"
+    assert B.df_ladder_variant(62, B.DF_FP64) == "gjb_o3"            # keyed by exact n_nu
+    for bad in [(96, B.DF_FP64, "gjb_o3"), (128, B.DF_FP64, "gjb_o4"), (64, B.DF_FP64, "mixed"),
+                (64, B.DF_FP32_REFINE, "vector"), (64, B.DF_FP32_REFINE, "fp32_o4"),
+                (96, B.DF_FP32_REFINE, "mixed_o4"), (64, B.DF_FP64, "mixed_o3"),
                 (64, B.DF_FP32, "mixed"), (64, B.DF_FP64, "fp32_o4"), (96, B.DF_FP32, "fp32")]:
         with pytest.raises(B.DfError) as e:
             B.df_ladder_set_variant(*bad)
@@ -176,7 +178,7 @@ def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     with pytest.raises(B.DfError):
         B.df_ladder_variant(130, B.DF_FP64)
     B.df_autotune_reset()
-    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb"
+    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3"
 
 
 def test_autotune_validates_before_any_gpu_work():

@@ -92,4 +92,4 @@ def test_autotune_records_choice_and_cache(B, tmp_path):
     finally:
         del os.environ["DF_TUNE_CACHE"]
     B.df_autotune_reset()
-    assert B.df_ladder_variant(48, B.DF_FP64) == "gjb"
+    assert B.df_ladder_variant(48, B.DF_FP64) == "gjb_o3"   # the untuned default
