@@ -383,7 +383,8 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
 }
 
 template <int NP>
-__global__ __launch_bounds__(NP * 4) void k_ladder_mixed(LadderArgs a0) {
+__global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_ladder_mixed(LadderArgs a0) {
     mixed_body<NP, true>(a0);
 }
 template <int NP>
