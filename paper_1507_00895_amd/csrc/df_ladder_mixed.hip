@@ -241,6 +241,16 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             Zr[tc] = f4{0, 0, 0, 0};
             Zi[tc] = f4{0, 0, 0, 0};
         }
+        // k = 4 s + lg; gamma rows of step s + 1 are requested once those of
+        // step s have arrived (the same pipelining as the residual below)
+        fv4 gv_nx[NT];
+        {
+            int k = lg;
+            asm volatile("" : "+v"(k));
+#pragma unroll
+            for (int tc = 0; tc < NT; ++tc)
+                gv_nx[tc] = ld4f(gp, (size_t)min(k, nm1) * n_nu + min(16 * tc + lj, nm1));
+        }
 #pragma unroll
         for (int kt = 0; kt < NT; ++kt) {
 #pragma unroll
@@ -249,15 +259,21 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             wave_sync_lds();
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
-                // an opaque row index keeps these loads inside their step: hoisted,
-                // all NT x 16 of them would be live at once
-                int k = 16 * kt + 4 * k4 + lg;
-                asm volatile("" : "+v"(k));
-                const cf xa = sh.Tw[w][lj][4 * k4 + lg];
+                const int st_ = 4 * kt + k4;
+                const int k = 4 * st_ + lg;
                 fv4 gv[NT];
 #pragma unroll
-                for (int tc = 0; tc < NT; ++tc)
-                    gv[tc] = ld4f(gp, (size_t)min(k, nm1) * n_nu + min(16 * tc + lj, nm1));
+                for (int tc = 0; tc < NT; ++tc) gv[tc] = gv_nx[tc];
+                __builtin_amdgcn_sched_barrier(0);
+                if (st_ + 1 < 4 * NT) {
+                    int kn = k + 4;
+                    asm volatile("" : "+v"(kn) : "v"(gv[0].x));
+#pragma unroll
+                    for (int tc = 0; tc < NT; ++tc)
+                        gv_nx[tc] = ld4f(gp, (size_t)min(kn, nm1) * n_nu + min(16 * tc + lj, nm1));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                const cf xa = sh.Tw[w][lj][4 * k4 + lg];
 #pragma unroll
                 for (int tc = 0; tc < NT; ++tc) {
                     const bool in = (k < n_nu) && (16 * tc + lj < n_nu);
@@ -300,29 +316,47 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             }
         }
 
-        // ---- E += gamma (chi Z0) on the FP64 matrix cores
+        // ---- E += gamma (chi Z0) on the FP64 matrix cores, k = 4 s + lg.  The
+        // operands of step s + 1 are requested once those of step s have
+        // arrived, so their latency hides behind step s's products (scheduling
+        // barriers keep the compiler from sinking the requests to their use).
         {
             const int lp = 4 * (lj & 3) + (lj >> 2);   // perm(lj)
             const int ia = 16 * w + lp;
+            const size_t rowa = (size_t)min(ia, nm1) * n_nu;
+            cd g_nx, x_nx;
+            {
+                int k = lg;
+                asm volatile("" : "+v"(k));
+                g_nx = ld(gam, rowa + min(k, nm1));
+                x_nx = ld(chi, (size_t)min(k, nm1) * N + q);
+            }
 #pragma unroll
-            for (int kt = 0; kt < NT; ++kt) {
+            for (int st_ = 0; st_ < 4 * NT; ++st_) {
+                const int k = 4 * st_ + lg;
+                const cd g0 = g_nx, xk = x_nx;
+                __builtin_amdgcn_sched_barrier(0);
+                if (st_ + 1 < 4 * NT) {
+                    int kn = k + 4;
+                    asm volatile("" : "+v"(kn) : "v"(g0.re), "v"(xk.re));
+                    g_nx = ld(gam, rowa + min(kn, nm1));
+                    x_nx = ld(chi, (size_t)min(kn, nm1) * N + q);
+                }
+                __builtin_amdgcn_sched_barrier(0);   // the requests stay ahead of the products
+                // no mask on gamma: rows k >= n_nu of Z0 are exactly zero (X is the
+                // identity there and gamma was masked in Z0), and rows ia >= n_nu of
+                // E only ever meet the exact zeros of X off its n_nu x n_nu block
+                const cd ga = g0;
+                cf z[NT];
 #pragma unroll
-                for (int k4 = 0; k4 < 4; ++k4) {
-                    int k = 16 * kt + 4 * k4 + lg;
-                    asm volatile("" : "+v"(k));
-                    const cd g0 = ld(gam, (size_t)min(ia, nm1) * n_nu + min(k, nm1));
-                    const cd xk = ld(chi, (size_t)min(k, nm1) * N + q);
-                    const bool in = (ia < n_nu) && (k < n_nu);
-                    const cd ga = in ? g0 : cd{0.0, 0.0};
+                for (int tc = 0; tc < NT; ++tc) z[tc] = sh.Zs[k][zs_col<NP>(k, 16 * tc + lj)];
 #pragma unroll
-                    for (int tc = 0; tc < NT; ++tc) {
-                        const cf z = sh.Zs[k][zs_col<NP>(k, 16 * tc + lj)];
-                        const cd b = xk * cd{(double)z.re, (double)z.im};
-                        Er[tc] = MT<double>::mma(ga.re, b.re, Er[tc]);
-                        Er[tc] = MT<double>::mma_na(ga.im, b.im, Er[tc]);
-                        Ei[tc] = MT<double>::mma(ga.re, b.im, Ei[tc]);
-                        Ei[tc] = MT<double>::mma(ga.im, b.re, Ei[tc]);
-                    }
+                for (int tc = 0; tc < NT; ++tc) {
+                    const cd b = xk * cd{(double)z[tc].re, (double)z[tc].im};
+                    Er[tc] = MT<double>::mma(ga.re, b.re, Er[tc]);
+                    Er[tc] = MT<double>::mma_na(ga.im, b.im, Er[tc]);
+                    Ei[tc] = MT<double>::mma(ga.re, b.im, Ei[tc]);
+                    Ei[tc] = MT<double>::mma(ga.im, b.re, Ei[tc]);
                 }
             }
         }
