@@ -976,8 +976,12 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         a.item0 = 0;
         a.n_items = s.items;
         for (int prec : precs) {
-        int best = -1;
-        float best_ms = 0.f;
+        // two rounds over the candidates, each variant keeping its faster
+        // round: a variant timed right after the slow pivoting kernels (or
+        // while clocks settle) is not judged on that round alone
+        float vms[LV_COUNT];
+        for (int v = 0; v < LV_COUNT; ++v) vms[v] = -1.f;
+        for (int round = 0; round < 2 && rc == DF_OK; ++round)
         for (int v = 0; v < LV_COUNT && rc == DF_OK; ++v) {
             if (!variant_supports(v, s.n_nu, prec)) continue;
             constexpr int kReps = 3;
@@ -992,11 +996,11 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
                                 hipEventSynchronize(e1) != hipSuccess ||
                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
                 rc = DF_E_HIP;
-            if (rc == DF_OK && (best < 0 || ms < best_ms)) {
-                best = v;
-                best_ms = ms;
-            }
+            if (rc == DF_OK && (vms[v] < 0.f || ms < vms[v])) vms[v] = ms;
         }
+        int best = -1;
+        for (int v = 0; v < LV_COUNT; ++v)
+            if (vms[v] >= 0.f && (best < 0 || vms[v] < vms[best])) best = v;
         if (rc == DF_OK && best >= 0) set_tuned_variant(prec, s.n_nu, best);
         }
     }
