@@ -1,0 +1,153 @@
+"""Pins of the lattice-observable oracle (Sec. 2.3) against what the paper and
+the mathematics fix: the lattice Dyson equation that the paper states between
+eqs. (sigma_lat) and (glat), the DMFT limit, the Hubbard atom's self-energy,
+brute-force momentum sums, the Neumann series of the ladder and symmetries.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import df_oracle as O
+from oracle import lattice as LT
+from paper_1507_00895_amd import inputs as I
+
+
+def _problem(D=2, nk=4, n_nu=8, n_om=3, beta=4.0, U=2.0, t=0.1):
+    return I.atomic_limit_problem(D, nk, n_nu, n_om, beta, U, t)
+
+
+def _symmetric_sigma(p):
+    """A dual self-energy with the symmetries of the converged one: the oracle's
+    own first iterations from zero (point group, Sigma~(-nu) = Sigma~(nu)*)."""
+    r = O.iterate(p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta, p.n_om,
+                  alpha=0.5, tol=0.0, max_iter=3)
+    return r.sigma
+
+
+def test_matsubara_window():
+    nu = LT.matsubara_nu(6, 2.0)
+    assert np.allclose(nu, np.array([-5, -3, -1, 1, 3, 5]) * math.pi / 2.0, rtol=1e-15)
+
+
+def _generic_inputs(seed, n_nu=8, N=16):
+    """Generic O(1) complex g, Delta, real eps and Sigma~: an algebraic identity
+    is tested away from the near-cancellations of particular physical inputs."""
+    rng = np.random.default_rng(seed)
+    c = lambda *sh: rng.standard_normal(sh) + 1j * rng.standard_normal(sh)
+    return c(n_nu), c(n_nu), rng.standard_normal(N), 0.3 * c(n_nu, N), 0.7, 3.0
+
+
+def test_l1_sigma_lat_and_g_lat_obey_the_lattice_dyson_equation():
+    """G_lat of eq. (glat) equals 1 / (i nu + mu - eps - Sigma_lat) for any Sigma~."""
+    for seed in (11, 12, 13):
+        g, delta, eps, S, mu, beta = _generic_inputs(seed)
+        G = O.dual_gf(O.dual_gf0(g, delta, eps), S)
+        Gl = LT.g_lat(G, g, delta, eps)
+        Sl = LT.sigma_lat(S, g, delta, mu, beta)
+        nu = LT.matsubara_nu(len(g), beta)[:, None]
+        dyson = 1.0 / (1j * nu + mu - eps[None, :] - Sl)
+        assert np.abs(Gl - dyson).max() <= 1e-12 * np.abs(Gl).max()
+
+
+def test_l1_printed_sign_would_fail_the_dyson_relation():
+    """The denominator 1 - g Sigma~ (the printed sign) breaks the stated relation."""
+    g, delta, eps, S, mu, beta = _generic_inputs(14)
+    G = O.dual_gf(O.dual_gf0(g, delta, eps), S)
+    Gl = LT.g_lat(G, g, delta, eps)
+    Sl_printed = S / (1.0 - g[:, None] * S) + LT.sigma_dmft(g, delta, mu, beta)[:, None]
+    nu = LT.matsubara_nu(len(g), beta)[:, None]
+    dyson = 1.0 / (1j * nu + mu - eps[None, :] - Sl_printed)
+    assert np.abs(Gl - dyson).max() > 1e-2 * np.abs(Gl).max()
+
+
+def test_l1_zero_dual_self_energy_gives_dmft():
+    """Sigma~ = 0: Sigma_lat = Sigma^DMFT and G_lat = frak G = [1/g + Delta - eps]^-1."""
+    g, delta, eps, S, mu, beta = _generic_inputs(15)
+    Z = np.zeros_like(S)
+    G0 = O.dual_gf0(g, delta, eps)
+    Sl = LT.sigma_lat(Z, g, delta, mu, beta)
+    sd = LT.sigma_dmft(g, delta, mu, beta)
+    assert np.allclose(Sl, np.broadcast_to(sd[:, None], Sl.shape), rtol=1e-15, atol=0)
+    g_dmft = 1.0 / (1.0 / g[:, None] + delta[:, None] - eps[None, :])
+    Gl = LT.g_lat(G0, g, delta, eps)
+    assert np.abs(Gl - g_dmft).max() <= 1e-12 * np.abs(g_dmft).max()
+    fg = LT.frak_g(G0, G0, g)
+    assert np.abs(fg - g_dmft).max() <= 1e-12 * np.abs(g_dmft).max()
+
+
+@pytest.mark.parametrize("U,beta", [(2.0, 4.0), (4.0, 10.0)])
+def test_sigma_dmft_of_the_half_filled_atom(U, beta):
+    """With the atomic g of eq. (atomic_limit1) and mu = U/2:
+    Sigma^DMFT + Delta = U/2 + U^2 / (4 i nu), the Hubbard atom's self-energy."""
+    p = I.atomic_limit_problem(2, 4, 10, 3, beta, U, 0.1)
+    nu = LT.matsubara_nu(p.n_nu, p.beta)
+    atom = U / 2 + U * U / (4j * nu)
+    got = LT.sigma_dmft(p.g, p.delta, p.mu, p.beta) + p.delta
+    assert np.abs(got - atom).max() <= 1e-13 * np.abs(atom).max()
+
+
+def _brute_lattice_bubble_sum(X, D, nk, beta):
+    """-(T/N) sum_{nu,k} X_{nu,k} X_{nu,k+q} by explicit loops over q and k."""
+    n_nu, N = X.shape
+    coords = list(np.ndindex(*((nk,) * D)))
+    index = {c: i for i, c in enumerate(coords)}
+    out = np.zeros(N, dtype=complex)
+    for q, qc in enumerate(coords):
+        s = 0j
+        for k, kc in enumerate(coords):
+            kq = index[tuple((a + b) % nk for a, b in zip(kc, qc))]
+            s += np.sum(X[:, k] * X[:, kq])
+        out[q] = -s / (beta * N)
+    return out
+
+
+def test_l2_zero_vertex_gives_the_lattice_bubble():
+    p = _problem()
+    S = _symmetric_sigma(p)
+    zero = np.zeros_like(p.gamma_uu)
+    ch, sp = LT.chi_lattice(S, p.g, p.delta, p.eps, zero, zero, p.D, p.nk, p.beta)
+    G = O.dual_gf(O.dual_gf0(p.g, p.delta, p.eps), S)
+    ref = _brute_lattice_bubble_sum(LT.g_lat(G, p.g, p.delta, p.eps), p.D, p.nk, p.beta)
+    assert np.abs(ch - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(sp - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_l3_ladder_term_matches_its_neumann_series():
+    """sum L Gamma L = sum_p L^T gamma (chi~ gamma)^p L for a vertex scaled into
+    the convergence radius; L by brute force, chi~ by the plain k-sum."""
+    p = _problem(n_nu=6)
+    S = _symmetric_sigma(p)
+    s = 0.2
+    guu, gud = s * p.gamma_uu, s * p.gamma_ud
+    ch, sp = LT.chi_lattice(S, p.g, p.delta, p.eps, guu, gud, p.D, p.nk, p.beta)
+    zero = np.zeros_like(guu)
+    ch0, _ = LT.chi_lattice(S, p.g, p.delta, p.eps, zero, zero, p.D, p.nk, p.beta)
+    G0 = O.dual_gf0(p.g, p.delta, p.eps)
+    G = O.dual_gf(G0, S)
+    fg = LT.frak_g(G, G0, p.g)
+    L = O.bubble_direct(fg, p.D, p.nk, 1, p.beta)[0]
+    chi0 = O.bubble_direct(G, p.D, p.nk, 1, p.beta)[0]
+    i0 = (p.n_om - 1) // 2
+    for c, got in ((0, ch), (1, sp)):
+        gam = guu[i0] + (gud[i0] if c == 0 else -gud[i0])
+        for q in range(p.N):
+            M = gam * chi0[None, :, q]
+            assert np.max(np.abs(np.linalg.eigvals(M))) < 0.5
+            term, total = gam @ L[:, q], 0j
+            for _ in range(200):
+                total += L[:, q] @ term
+                term = M @ term
+            assert abs((got[q] - ch0[q]) - total) <= 1e-12 * max(abs(total), 1e-300)
+
+
+def test_chi_is_real_and_point_group_invariant_at_zero_frequency():
+    p = _problem(nk=6, n_nu=8)
+    S = _symmetric_sigma(p)
+    ch, sp = LT.chi_lattice(S, p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta)
+    for x in (ch, sp):
+        assert np.abs(x.imag).max() <= 1e-12 * np.abs(x).max()
+        X = x.reshape(p.nk, p.nk)
+        minus = (-np.arange(p.nk)) % p.nk
+        assert np.allclose(X, X.T, rtol=1e-11, atol=1e-14 * np.abs(X).max())
+        assert np.allclose(X, X[minus, :], rtol=1e-11, atol=1e-14 * np.abs(X).max())
