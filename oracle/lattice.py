@@ -34,6 +34,8 @@ gamma_uu, gamma_ud [n_om][n_nu][n_nu]; chi~ [n_om][n_nu][N].
 """
 from __future__ import annotations
 
+from fractions import Fraction
+
 import numpy as np
 
 from . import df_oracle as O
@@ -58,11 +60,54 @@ def sigma_lat(sigma: np.ndarray, g: np.ndarray, delta: np.ndarray, mu: float,
     return sigma / (1.0 + gg * sigma) + sigma_dmft(g, delta, mu, beta)[:, None]
 
 
-def g_lat(G: np.ndarray, g: np.ndarray, delta: np.ndarray, eps: np.ndarray) -> np.ndarray:
-    """G_{nu,k} = a + a g^-1 G~ g^-1 a with a = [Delta_nu - eps_k]^-1  (eq. glat)."""
-    a = 1.0 / (np.asarray(delta)[:, None] - np.asarray(eps)[None, :])
-    ginv = 1.0 / np.asarray(g)[:, None]
-    return a + a * ginv * G * ginv * a
+class _Q:
+    """Complex number with exact rational parts (fractions.Fraction)."""
+    __slots__ = ("re", "im")
+
+    def __init__(self, re, im=0):
+        self.re, self.im = Fraction(re), Fraction(im)
+
+    def __add__(self, o):
+        return _Q(self.re + o.re, self.im + o.im)
+
+    def __sub__(self, o):
+        return _Q(self.re - o.re, self.im - o.im)
+
+    def __mul__(self, o):
+        return _Q(self.re * o.re - self.im * o.im, self.re * o.im + self.im * o.re)
+
+    def inv(self):
+        d = self.re * self.re + self.im * self.im
+        return _Q(self.re / d, -self.im / d)
+
+    def to_complex(self) -> complex:
+        return complex(float(self.re), float(self.im))
+
+
+def g_lat(sigma, g: np.ndarray, delta: np.ndarray, eps: np.ndarray) -> np.ndarray:
+    """G_{nu,k} = a + a g^-1 G~ g^-1 a with a = [Delta_nu - eps_k]^-1  (eq. glat), G~ from
+    eqs. (gd0) and (dyson) with self-energy sigma (None = zero).
+
+    Evaluated exactly, in rational arithmetic on the FP64 inputs, and rounded once:
+    where Delta - eps is small the two terms of eq. (glat) are large and cancel
+    (to a part in 1e4-1e6 on the workloads of the tests), and G~0 is itself a
+    small difference of O(g) terms there, so that FP64 (and even long double)
+    arithmetic loses up to 1e-10 of the result.
+    """
+    n_nu, N = len(g), len(eps)
+    out = np.empty((n_nu, N), dtype=np.complex128)
+    for n in range(n_nu):
+        gq = _Q(float(np.real(g[n])), float(np.imag(g[n])))
+        ginv = gq.inv()
+        for k in range(N):
+            dme = _Q(float(np.real(delta[n])) - Fraction(float(eps[k])), float(np.imag(delta[n])))
+            G = (ginv + dme).inv() - gq                                   # eq. (gd0)
+            if sigma is not None:
+                S = _Q(float(np.real(sigma[n, k])), float(np.imag(sigma[n, k])))
+                G = (G.inv() - S).inv()                                   # eq. (dyson)
+            a = dme.inv()
+            out[n, k] = (a + a * ginv * G * ginv * a).to_complex()
+    return out
 
 
 def frak_g(G: np.ndarray, G0: np.ndarray, g: np.ndarray) -> np.ndarray:
@@ -77,18 +122,20 @@ def lattice_bubble0(X: np.ndarray, D: int, nk: int, beta: float) -> np.ndarray:
 
 def chi_lattice(sigma: np.ndarray, g: np.ndarray, delta: np.ndarray, eps: np.ndarray,
                 gamma_uu: np.ndarray, gamma_ud: np.ndarray, D: int, nk: int,
-                beta: float):
+                beta: float, Gl: np.ndarray = None):
     """chi^{ch/sp}(Omega = 0, q) of the dual solution with self-energy sigma.
 
     chi = -(T/N) sum_{nu,k} G_{nu,k} G_{nu,k+q} + sum_{nu,nu'} L_nu Gamma_{nu nu'} L_nu'
     with L_nu(q) = -(T/N) sum_k frakG_{nu,k} frakG_{nu,k+q} and Gamma = solve(1 - gamma chi~, gamma)
-    at Omega = 0 (index (n_om - 1) / 2 of the vertex arrays).  Returns (chi_ch, chi_sp), [N] each.
+    at Omega = 0 (index (n_om - 1) / 2 of the vertex arrays).  Gl: g_lat(sigma, ...) if the
+    caller has it.  Returns (chi_ch, chi_sp), [N] each.
     """
     n_om = gamma_uu.shape[0]
     i0 = (n_om - 1) // 2
     G0 = O.dual_gf0(g, delta, eps)
     G = O.dual_gf(G0, sigma)
-    Gl = g_lat(G, g, delta, eps)
+    if Gl is None:
+        Gl = g_lat(sigma, g, delta, eps)
     bub = lattice_bubble0(Gl, D, nk, beta).sum(axis=0)           # [N]
     L = lattice_bubble0(frak_g(G, G0, g), D, nk, beta)           # [n_nu][N]
     chi0 = O.bubble_fft(G, D, nk, 1, beta)[0]                    # chi~ at Omega = 0

@@ -6,7 +6,9 @@ library has not been built, or no GPU is present, the calls raise; there is no
 CPU fallback.
 
 Same names as the ABI: df_workspace_size, df_dual_gf, df_bubble,
-df_ladder_solve, df_sigma, df_iterate, df_strerror, df_version.
+df_ladder_solve, df_sigma, df_iterate, df_strerror, df_version, the autotuner
+calls, the warm-start network (df_mlp_*) and the lattice observables
+(df_lattice_workspace_size, df_lattice).
 """
 from __future__ import annotations
 
@@ -284,6 +286,60 @@ LADDER_VARIANTS = ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32
 
 def df_autotune_reset():
     return _check("df_autotune_reset", load().df_autotune_reset())
+
+
+# ---------------------------------------------------------------------------
+# lattice observables (include/df_lattice.h)
+# ---------------------------------------------------------------------------
+LATTICE_EXPORTED = ("df_lattice_workspace_size", "df_lattice")
+
+
+def _lattice_lib():
+    lib = load()
+    if getattr(lib, "_lattice_ready", False):
+        return lib
+    P = ctypes.POINTER
+    lib.df_lattice_workspace_size.argtypes = [P(DfInst), P(ctypes.c_size_t)]
+    lib.df_lattice.argtypes = [P(DfInst), ctypes.c_double] + [ctypes.c_void_p] * 4 + \
+        [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    for name in LATTICE_EXPORTED:
+        getattr(lib, name).restype = ctypes.c_int
+    lib._lattice_ready = True
+    return lib
+
+
+def df_lattice_workspace_size(inst: Instance) -> int:
+    n = ctypes.c_size_t(0)
+    c = inst.to_c()
+    _check("df_lattice_workspace_size",
+           _lattice_lib().df_lattice_workspace_size(ctypes.byref(c), ctypes.byref(n)))
+    return int(n.value)
+
+
+def lattice_workspace(inst: Instance, device="cuda"):
+    """A torch uint8 device buffer of the size df_lattice asks for (256-B aligned)."""
+    import torch
+    nbytes = df_lattice_workspace_size(inst)
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-int(buf.data_ptr())) % 256
+    return buf[off:off + nbytes]
+
+
+def df_lattice(inst: Instance, mu: float, sigma_lat=None, g_lat=None, chi_ch=None, chi_sp=None,
+               ws=None, stream=None):
+    """Lattice observables of inst (its sigma = the dual self-energy): writes the given
+    complex128 device tensors sigma_lat, g_lat [n_nu][N] and chi_ch, chi_sp [N]."""
+    import torch
+    for name, t in (("sigma_lat", sigma_lat), ("g_lat", g_lat), ("chi_ch", chi_ch),
+                    ("chi_sp", chi_sp)):
+        if t is not None and (t.dtype != torch.complex128 or not t.is_contiguous() or not t.is_cuda):
+            raise TypeError(f"{name} must be a contiguous complex128 device tensor")
+    if ws is None:
+        ws = lattice_workspace(inst, device=inst.g.device)
+    c = inst.to_c()
+    return _check("df_lattice", _lattice_lib().df_lattice(
+        ctypes.byref(c), float(mu), _ptr(sigma_lat), _ptr(g_lat), _ptr(chi_ch), _ptr(chi_sp),
+        _ptr(ws), ws.numel(), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

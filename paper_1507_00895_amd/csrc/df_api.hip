@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/df.h"
+#include "../../include/df_lattice.h"
 #include "df_internal.hpp"
 #include "df_tune.hpp"
 
@@ -568,6 +569,38 @@ bool acc_weights(const AccState &S, int slots, int newest, double *coef) {
     return true;
 }
 
+// ---- lattice observables (df_lattice.h) ---------------------------------------
+constexpr int kLatticeChunk = 512;   // (channel, q) items per elimination launch
+
+struct LatticeLayout {
+    size_t gd, fg, gl, gr, chi0, L, bub, lad, work;
+    int chunk;
+    size_t total;
+};
+
+LatticeLayout lattice_layout_of(const Shape &s) {
+    LatticeLayout L;
+    const size_t fld = (size_t)s.n_nu * s.N * 16;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.gd = take(fld);
+    L.fg = take(fld);
+    L.gl = take(fld);
+    L.gr = take(fld);
+    L.chi0 = take(fld);
+    L.L = take(fld);
+    L.bub = take(fld);
+    L.lad = take(2 * (size_t)s.N * 16);
+    L.chunk = 2 * s.N < kLatticeChunk ? 2 * s.N : kLatticeChunk;
+    L.work = take((size_t)L.chunk * s.n_nu * (s.n_nu + 1) * 16);
+    L.total = o;
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1033,6 +1066,88 @@ int df_ladder_set_variant(int32_t n_nu, int32_t prec, const char *name) {
 
 int df_autotune_reset(void) {
     clear_tuned();
+    return DF_OK;
+}
+
+int df_lattice_workspace_size(const df_inst_t *inst, size_t *bytes) {
+    if (!inst || !bytes) return DF_E_INVAL;
+    Shape s;
+    const int rc = check_inst(*inst, &s);
+    if (rc != DF_OK) return rc;
+    *bytes = lattice_layout_of(s).total;
+    return DF_OK;
+}
+
+int df_lattice(const df_inst_t *inst, double mu, double *sigma_lat, double *g_lat, double *chi_ch,
+               double *chi_sp, void *ws, size_t ws_bytes, df_stream_t stream) {
+    if (!inst) return DF_E_INVAL;
+    const df_inst_t &p = *inst;
+    Shape s;
+    int rc = check_inst(p, &s);
+    if (rc != DF_OK) return rc;
+    if (!isfinite(mu)) return DF_E_INVAL;
+    if (!p.g || !p.delta || !p.eps) return DF_E_INVAL;
+    const bool want_chi = chi_ch || chi_sp;
+    if (want_chi && (!p.gamma_uu || !p.gamma_ud)) return DF_E_INVAL;
+    const LatticeLayout L = lattice_layout_of(s);
+    if (!ws || (((uintptr_t)ws) & (kAlign - 1)) || ws_bytes < L.total) return DF_E_WORKSPACE;
+    rc = ensure_attrs();
+    if (rc != DF_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+
+    LatticeFieldArgs f{};
+    f.n_nu = s.n_nu;
+    f.N = s.N;
+    f.beta = p.beta;
+    f.mu = mu;
+    f.g = p.g;
+    f.delta = p.delta;
+    f.eps = p.eps;
+    f.sigma = p.sigma;
+    f.sigma_lat = sigma_lat;
+    f.g_lat = g_lat;
+    f.gl = at<double>(ws, L.gl);
+    f.gd = at<double>(ws, L.gd);
+    f.fg = at<double>(ws, L.fg);
+    HIPCHK(launch_lattice_fields(f, st));
+    if (!want_chi) return DF_OK;
+
+    // chi~, L and the per-nu lattice bubble at Omega = 0: the iteration's FFT bubble
+    // with a one-frequency bosonic window
+    Shape s1 = s;
+    s1.n_om = 1;
+    double *gr = at<double>(ws, L.gr);
+    rc = stage_transform_gd(s1, f.gd, gr, st);
+    if (rc == DF_OK) rc = stage_bubble(p, s1, gr, at<double>(ws, L.chi0), st);
+    if (rc == DF_OK) rc = stage_transform_gd(s1, f.fg, gr, st);
+    if (rc == DF_OK) rc = stage_bubble(p, s1, gr, at<double>(ws, L.L), st);
+    if (rc == DF_OK) rc = stage_transform_gd(s1, f.gl, gr, st);
+    if (rc == DF_OK) rc = stage_bubble(p, s1, gr, at<double>(ws, L.bub), st);
+    if (rc != DF_OK) return rc;
+
+    LatticeChiArgs c{};
+    c.n_nu = s.n_nu;
+    c.N = s.N;
+    c.i0 = (s.n_om - 1) / 2;
+    c.guu = p.gamma_uu;
+    c.gud = p.gamma_ud;
+    c.L = at<double>(ws, L.L);
+    c.chi0 = at<double>(ws, L.chi0);
+    c.work = at<double>(ws, L.work);
+    c.lad = at<double>(ws, L.lad);
+    for (int i0 = 0; i0 < 2 * s.N; i0 += L.chunk) {
+        c.item0 = i0;
+        const int items = (2 * s.N - i0) < L.chunk ? (2 * s.N - i0) : L.chunk;
+        HIPCHK(launch_lattice_chi_ladder(c, items, st));
+    }
+    LatticeSumArgs m{};
+    m.n_nu = s.n_nu;
+    m.N = s.N;
+    m.bub = at<double>(ws, L.bub);
+    m.lad = c.lad;
+    m.chi_ch = chi_ch;
+    m.chi_sp = chi_sp;
+    HIPCHK(launch_lattice_chi_sum(m, st));
     return DF_OK;
 }
 

@@ -146,6 +146,30 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
     return x * per + (x < rem ? x : rem) + i;
 }
 
+// Lattice observables (df_lattice.hip)
+struct LatticeFieldArgs {
+    int n_nu, N;
+    double beta, mu;
+    const double *g, *delta, *eps, *sigma;   // sigma may be null (Sigma~ = 0)
+    double *sigma_lat, *g_lat;               // outputs, may be null
+    double *gl, *gd, *fg;                    // [n_nu][N] G_lat, G~, frak G
+};
+
+struct LatticeChiArgs {
+    int n_nu, N, i0;                         // i0: index of Omega = 0 in the vertex arrays
+    int item0;                               // first item (c * N + q) of this launch
+    const double *guu, *gud;                 // [n_om][n_nu][n_nu]
+    const double *L, *chi0;                  // [n_nu][N]
+    double *work;                            // [items][n_nu][n_nu + 1] complex
+    double *lad;                             // [2][N]
+};
+
+struct LatticeSumArgs {
+    int n_nu, N;
+    const double *bub, *lad;                 // [n_nu][N], [2][N]
+    double *chi_ch, *chi_sp;                 // [N], may be null
+};
+
 hipError_t launch_dual_gf(const DualGfArgs &a, hipStream_t s);
 hipError_t launch_bubble(const BubbleArgs &a, hipStream_t s);
 hipError_t launch_sigma_part(const SigmaArgs &a, hipStream_t s);
@@ -177,5 +201,8 @@ hipError_t launch_ladder_fp32(const LadderArgs &a, int occ, hipStream_t s);
 // pivoting kernel over a device-side queue of items (grid-stride, fixed grid)
 hipError_t launch_ladder_fp64_queue(const LadderArgs &a, int blocks, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
+hipError_t launch_lattice_fields(const LatticeFieldArgs &a, hipStream_t s);
+hipError_t launch_lattice_chi_ladder(const LatticeChiArgs &a, int items, hipStream_t s);
+hipError_t launch_lattice_chi_sum(const LatticeSumArgs &a, hipStream_t s);
 
 }  // namespace df

@@ -12,7 +12,7 @@ import pytest
 from paper_1507_00895_amd import binding as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("df.h", "df_mlp.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("df.h", "df_mlp.h", "df_lattice.h")]
 
 
 def declared_functions():
@@ -32,7 +32,7 @@ def test_every_header_is_checked():
 def test_library_exports_every_declared_symbol():
     lib = B.load()
     decl = declared_functions()
-    assert set(decl) == set(B.EXPORTED) | set(B.MLP_EXPORTED)
+    assert set(decl) == set(B.EXPORTED) | set(B.MLP_EXPORTED) | set(B.LATTICE_EXPORTED)
     for name in decl:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
@@ -186,3 +186,32 @@ def test_autotune_validates_before_any_gpu_work():
     assert lib.df_autotune(None, 1, None, None, 0, None) == B.DF_E_INVAL
     arr = (B.DfInst * 1)(_inst())
     assert lib.df_autotune(arr, 1, None, None, 0, None) == B.DF_E_WORKSPACE
+
+
+def test_lattice_argument_validation():
+    """df_lattice rejects bad instances, mu and workspaces before any HIP work."""
+    lib = B._lattice_lib()
+    n = ctypes.c_size_t(0)
+    good = _inst(n_om=3)
+    assert lib.df_lattice_workspace_size(ctypes.byref(good), ctypes.byref(n)) == B.DF_OK
+    N, n_nu = 64, 16
+    fld = n_nu * N * 16
+    chunk = min(2 * N, 512)
+    assert n.value >= 7 * fld + 2 * N * 16 + chunk * n_nu * (n_nu + 1) * 16
+    assert lib.df_lattice_workspace_size(None, ctypes.byref(n)) == B.DF_E_INVAL
+    bad = _inst(n_nu=15)
+    assert lib.df_lattice_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == B.DF_E_INVAL
+    big = _inst(n_nu=130)
+    assert lib.df_lattice_workspace_size(ctypes.byref(big), ctypes.byref(n)) == B.DF_E_UNSUPPORTED
+    fake = 0x1000
+    args = [fake, fake, fake, fake]
+    assert lib.df_lattice(ctypes.byref(good), float("nan"), *args, fake * 256, 1 << 40,
+                          None) == B.DF_E_INVAL
+    assert lib.df_lattice(ctypes.byref(good), 1.0, *args, None, 1 << 40, None) == B.DF_E_WORKSPACE
+    assert lib.df_lattice(ctypes.byref(good), 1.0, *args, fake + 8, 1 << 40,
+                          None) == B.DF_E_WORKSPACE
+    assert lib.df_lattice(ctypes.byref(good), 1.0, *args, fake * 256, 16, None) == B.DF_E_WORKSPACE
+    nog = _inst(n_om=3)
+    nog.gamma_uu = None
+    assert lib.df_lattice(ctypes.byref(nog), 1.0, *args, fake * 256, 1 << 40,
+                          None) == B.DF_E_INVAL

@@ -1,0 +1,114 @@
+"""Parity of df_lattice (HIP, through the C ABI) with the lattice-observable
+oracle, on the same dual self-energy.  Error metric: max|X - X_ref| / max|X_ref|
+per array; FP64 throughout, so the bar is 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle import df_oracle as O
+from oracle import lattice as LT
+from paper_1507_00895_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def rel(x, ref):
+    den = np.abs(ref).max()
+    return float(np.abs(x - ref).max() / den)
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1507_00895_amd import binding
+    binding.load()
+    return binding
+
+
+def _outputs(p):
+    import torch
+    c = dict(dtype=torch.complex128, device="cuda")
+    return (torch.full((p.n_nu, p.N), np.nan, **c), torch.full((p.n_nu, p.N), np.nan, **c),
+            torch.full((p.N,), np.nan, **c), torch.full((p.N,), np.nan, **c))
+
+
+def _sigma(B, p, x, iters):
+    """A dual self-energy from the GPU loop (iters linear-mixing steps from zero)."""
+    import torch
+    ws = B.workspace([x])
+    B.df_iterate([x], ws, B.make_opts(mix=0.5, tol=0.0, max_iter=iters),
+                 allow=(B.DF_OK, B.DF_W_FALLBACK))
+    torch.cuda.synchronize()
+    return x.sigma.cpu().numpy()
+
+
+def _check_all(B, p, x, S):
+    import torch
+    sl, gl, ch, sp = _outputs(p)
+    print(f"df_lattice D={p.D} nk={p.nk} n_nu={p.n_nu} n_om={p.n_om}", flush=True)
+    B.df_lattice(x, p.mu, sl, gl, ch, sp)
+    torch.cuda.synchronize()
+    Sref = np.zeros((p.n_nu, p.N), complex) if S is None else S
+    assert rel(sl.cpu().numpy(), LT.sigma_lat(Sref, p.g, p.delta, p.mu, p.beta)) <= TOL64
+    Gl = LT.g_lat(S, p.g, p.delta, p.eps)
+    assert rel(gl.cpu().numpy(), Gl) <= TOL64
+    rch, rsp = LT.chi_lattice(Sref, p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta,
+                              Gl=Gl)
+    assert rel(ch.cpu().numpy(), rch) <= TOL64
+    assert rel(sp.cpu().numpy(), rsp) <= TOL64
+
+
+# (D, nk, n_nu, n_om, beta, U, t, iterations)
+CASES = [
+    (2, 8, 16, 1, 10.0, 2.0, 0.1, 10),    # the small 2D workload (Omega = 0 only)
+    (2, 8, 16, 5, 10.0, 2.0, 0.1, 6),
+    (2, 4, 14, 3, 5.0, 2.0, 0.2, 4),      # smallest grid, n_nu not a multiple of 16
+    (1, 64, 20, 7, 10.0, 2.0, 0.1, 4),    # 1D
+    (3, 4, 8, 3, 15.0, 3.0, 0.182358, 3),  # 3D
+    (2, 32, 16, 3, 20.0, 1.0, 0.1, 3),    # 2048 (channel, q) items: four elimination chunks
+    (2, 4, 128, 3, 10.0, 2.0, 0.1, 2),    # largest n_nu
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"D{c[0]}nk{c[1]}nu{c[2]}om{c[3]}")
+def test_lattice_matches_oracle(B, case):
+    D, nk, n_nu, n_om, beta, U, t, iters = case
+    p = I.atomic_limit_problem(D, nk, n_nu, n_om, beta, U, t)
+    x = B.make_instance(p)
+    S = _sigma(B, p, x, iters)
+    _check_all(B, p, x, S)
+
+
+def test_lattice_zero_sigma_and_null_outputs(B):
+    """sigma NULL (Sigma~ = 0: the DMFT limit), and each output alone."""
+    import torch
+    p = I.atomic_limit_problem(2, 8, 16, 3, 10.0, 2.0, 0.1)
+    x = B.make_instance(p)
+    x.sigma = None
+    _check_all(B, p, x, None)
+    Z = np.zeros((p.n_nu, p.N), complex)
+    sl, gl, ch, sp = _outputs(p)
+    B.df_lattice(x, p.mu, sigma_lat=sl)
+    B.df_lattice(x, p.mu, chi_sp=sp)
+    torch.cuda.synchronize()
+    assert rel(sl.cpu().numpy(), LT.sigma_lat(Z, p.g, p.delta, p.mu, p.beta)) <= TOL64
+    assert np.isnan(gl.cpu().numpy()).all() and np.isnan(ch.cpu().numpy()).all()
+    _, rsp = LT.chi_lattice(Z, p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta)
+    assert rel(sp.cpu().numpy(), rsp) <= TOL64
+
+
+def test_lattice_at_the_converged_bench_solution(B):
+    """The 32x32, n_nu = 64, n_om = 31 workload at its converged Sigma~ (U = 2):
+    every observable against the oracle, the susceptibilities at all 1024 q."""
+    import torch
+    p = [q for q in I.workload_square32() if q.U == 2.0][0]
+    x = B.make_instance(p)
+    ws = B.workspace([x], B.make_opts(accel=5))
+    code, it, d = B.df_iterate([x], ws, B.make_opts(mix=0.5, tol=1e-10, max_iter=200, accel=5),
+                               allow=(B.DF_OK, B.DF_W_FALLBACK))
+    torch.cuda.synchronize()
+    assert d[0] < 1e-10
+    _check_all(B, p, x, x.sigma.cpu().numpy())

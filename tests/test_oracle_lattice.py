@@ -42,8 +42,7 @@ def test_l1_sigma_lat_and_g_lat_obey_the_lattice_dyson_equation():
     """G_lat of eq. (glat) equals 1 / (i nu + mu - eps - Sigma_lat) for any Sigma~."""
     for seed in (11, 12, 13):
         g, delta, eps, S, mu, beta = _generic_inputs(seed)
-        G = O.dual_gf(O.dual_gf0(g, delta, eps), S)
-        Gl = LT.g_lat(G, g, delta, eps)
+        Gl = LT.g_lat(S, g, delta, eps)
         Sl = LT.sigma_lat(S, g, delta, mu, beta)
         nu = LT.matsubara_nu(len(g), beta)[:, None]
         dyson = 1.0 / (1j * nu + mu - eps[None, :] - Sl)
@@ -53,8 +52,7 @@ def test_l1_sigma_lat_and_g_lat_obey_the_lattice_dyson_equation():
 def test_l1_printed_sign_would_fail_the_dyson_relation():
     """The denominator 1 - g Sigma~ (the printed sign) breaks the stated relation."""
     g, delta, eps, S, mu, beta = _generic_inputs(14)
-    G = O.dual_gf(O.dual_gf0(g, delta, eps), S)
-    Gl = LT.g_lat(G, g, delta, eps)
+    Gl = LT.g_lat(S, g, delta, eps)
     Sl_printed = S / (1.0 - g[:, None] * S) + LT.sigma_dmft(g, delta, mu, beta)[:, None]
     nu = LT.matsubara_nu(len(g), beta)[:, None]
     dyson = 1.0 / (1j * nu + mu - eps[None, :] - Sl_printed)
@@ -70,7 +68,7 @@ def test_l1_zero_dual_self_energy_gives_dmft():
     sd = LT.sigma_dmft(g, delta, mu, beta)
     assert np.allclose(Sl, np.broadcast_to(sd[:, None], Sl.shape), rtol=1e-15, atol=0)
     g_dmft = 1.0 / (1.0 / g[:, None] + delta[:, None] - eps[None, :])
-    Gl = LT.g_lat(G0, g, delta, eps)
+    Gl = LT.g_lat(None, g, delta, eps)
     assert np.abs(Gl - g_dmft).max() <= 1e-12 * np.abs(g_dmft).max()
     fg = LT.frak_g(G0, G0, g)
     assert np.abs(fg - g_dmft).max() <= 1e-12 * np.abs(g_dmft).max()
@@ -107,8 +105,7 @@ def test_l2_zero_vertex_gives_the_lattice_bubble():
     S = _symmetric_sigma(p)
     zero = np.zeros_like(p.gamma_uu)
     ch, sp = LT.chi_lattice(S, p.g, p.delta, p.eps, zero, zero, p.D, p.nk, p.beta)
-    G = O.dual_gf(O.dual_gf0(p.g, p.delta, p.eps), S)
-    ref = _brute_lattice_bubble_sum(LT.g_lat(G, p.g, p.delta, p.eps), p.D, p.nk, p.beta)
+    ref = _brute_lattice_bubble_sum(LT.g_lat(S, p.g, p.delta, p.eps), p.D, p.nk, p.beta)
     assert np.abs(ch - ref).max() <= 1e-13 * np.abs(ref).max()
     assert np.abs(sp - ref).max() <= 1e-13 * np.abs(ref).max()
 
@@ -151,3 +148,21 @@ def test_chi_is_real_and_point_group_invariant_at_zero_frequency():
         minus = (-np.arange(p.nk)) % p.nk
         assert np.allclose(X, X.T, rtol=1e-11, atol=1e-14 * np.abs(X).max())
         assert np.allclose(X, X[minus, :], rtol=1e-11, atol=1e-14 * np.abs(X).max())
+
+
+@pytest.mark.parametrize("nk,n_nu,beta", [(8, 64, 20.0), (4, 128, 10.0)])
+def test_g_lat_closed_form_used_by_the_kernel(nk, n_nu, beta):
+    """eq. (glat) with G~ of eqs. (gd0), (dyson) equals g (1 + g S) / (1 + g (Delta - eps)(1 + g S)),
+    the form the GPU kernel evaluates; that form in FP64 stays within 1e-12 of the printed
+    one evaluated exactly, where the printed one in FP64 does not."""
+    p = I.atomic_limit_problem(2, nk, n_nu, 3, beta, 2.0, 0.1)
+    rng = np.random.default_rng(7)
+    S = 0.05 * (rng.standard_normal((p.n_nu, p.N)) + 1j * rng.standard_normal((p.n_nu, p.N)))
+    G = O.dual_gf(O.dual_gf0(p.g, p.delta, p.eps), S)
+    ref = LT.g_lat(S, p.g, p.delta, p.eps)                      # exact, rounded once
+    gg, h = p.g[:, None], 1 + p.g[:, None] * S
+    closed = gg * h / (1 + gg * (p.delta[:, None] - p.eps[None, :]) * h)
+    assert np.abs(closed - ref).max() <= 1e-12 * np.abs(ref).max()
+    a = 1.0 / (p.delta[:, None] - p.eps[None, :])
+    fp64 = a + a / gg * G / gg * a
+    assert np.abs(fp64 - ref).max() > 1e-11 * np.abs(ref).max()
