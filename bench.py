@@ -205,6 +205,32 @@ def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
             "algorithmic_flops_per_launch": flops_launch}
 
 
+def lattice_leg(B, problems, insts, stream, log):
+    """df_lattice (Sigma_lat, G_lat, chi^{ch/sp} at Omega = 0) on each instance's last
+    converged Sigma~: time per instance (HIP events) and where chi^sp peaks."""
+    import numpy as np
+    import torch
+    out = []
+    for p, x in zip(problems, insts):
+        c = dict(dtype=torch.complex128, device=x.g.device)
+        sl, gl = torch.empty((p.n_nu, p.N), **c), torch.empty((p.n_nu, p.N), **c)
+        ch, sp = torch.empty(p.N, **c), torch.empty(p.N, **c)
+        ws = B.lattice_workspace(x, device=x.g.device)
+        B.df_lattice(x, p.mu, sl, gl, ch, sp, ws=ws, stream=stream.cuda_stream)   # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.df_lattice(x, p.mu, sl, gl, ch, sp, ws=ws, stream=stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        s = sp.cpu().numpy().real
+        q = int(np.argmax(s))
+        Q = sum((p.nk // 2) * p.nk ** a for a in range(p.D))
+        out.append({"U": p.U, "ms": e0.elapsed_time(e1), "chi_sp_max": float(s[q]),
+                    "chi_sp_peak_at_Q": q == Q, "chi_ch_at_Q": float(ch.cpu().numpy().real[Q])})
+    log(f"lattice observables: {[round(o['ms'], 2) for o in out]} ms per instance")
+    return out
+
+
 def warm_start_leg(problems, args, log):
     """Train the warm-start network on the method's own converged Sigma~ at
     this workload's shape, then predict the three instances' Sigma~."""
@@ -341,6 +367,7 @@ def main():
                                "converged": conv}
                 log(f"{name}: {sec:.3f} s per converged Sigma~")
             paths["warm_network"] = info
+        paths["lattice_observables"] = lattice_leg(B, problems, insts, stream, log)
 
     out = {
         "metric": "ladder (q,omega) solves/s + s per converged Sigma~: FP64 vs FP32-MFMA+refine at 1e-9 rel",

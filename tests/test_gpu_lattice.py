@@ -112,3 +112,8 @@ def test_lattice_at_the_converged_bench_solution(B):
     torch.cuda.synchronize()
     assert d[0] < 1e-10
     _check_all(B, p, x, x.sigma.cpu().numpy())
+    # the half-filled square lattice: antiferromagnetic spin correlations peak at Q = (pi, pi)
+    sp = torch.zeros(p.N, dtype=torch.complex128, device="cuda")
+    B.df_lattice(x, p.mu, chi_sp=sp)
+    torch.cuda.synchronize()
+    assert int(np.argmax(sp.cpu().numpy().real)) == (p.nk // 2) * p.nk + p.nk // 2
