@@ -134,7 +134,14 @@ def cpu_baseline(problems, budget_s: float = 20.0):
                        f"est. {t_iter:.1f} s per iteration")}
 
 
-def ladder_launch_ms(B, insts, ws, prec, stream, reps):
+def orbit_count(D, nk):
+    """Orbits of the hypercubic point group (axis permutations, k_a -> -k_a) on the q-grid."""
+    import itertools
+    return len({tuple(sorted(min(c, (nk - c) % nk) for c in q))
+                for q in itertools.product(range(nk), repeat=D)})
+
+
+def ladder_launch_ms(B, insts, ws, prec, stream, reps, symmetry=0):
     """Average duration of one ladder launch (one instance), HIP events on the launch stream."""
     import numpy as np
     import torch
@@ -143,14 +150,15 @@ def ladder_launch_ms(B, insts, ws, prec, stream, reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        B.df_ladder_solve(insts, ws, B.make_opts(prec=prec), stream=stream.cuda_stream)
+        B.df_ladder_solve(insts, ws, B.make_opts(prec=prec, symmetry=symmetry),
+                          stream=stream.cuda_stream)
         e1.record(stream)
         e1.synchronize()
         ms.append(e0.elapsed_time(e1))
     return float(np.mean(ms)) / len(insts)
 
 
-def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None, accel=0):
+def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None, accel=0, symmetry=0):
     """Cold (or given) start to tol 1e-8, one instance at a time (DF_ADAPTIVE:
     FP32 ladders down to a diff of 1e-4, FP64 after; accel > 0: Anderson
     acceleration over accel + 1 iterates)."""
@@ -165,7 +173,7 @@ def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None, acce
         ta = time.perf_counter()
         code, it, d = B.df_iterate([x], ws, B.make_opts(prec=prec, mix=0.5, tol=1e-8, max_iter=500,
                                                         use_graph=graph, switch_tol=1e-4,
-                                                        accel=accel),
+                                                        accel=accel, symmetry=symmetry),
                                    stream=stream.cuda_stream,
                                    allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
         stream.synchronize()
@@ -356,11 +364,27 @@ def main():
                            "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
                            "accel": ACCEL, "converged": conv}
             log(f"{name}: {paths[name]['s_per_converged_sigma']:.3f} s per converged Sigma~")
+        # symmetry-reduced ladders (one q per point-group orbit, Omega >= 0): a different
+        # unit of work, so reported apart; "effective" rates count the full 2 n_om N ladders
+        ms = ladder_launch_ms(B, insts, ws, B.DF_FP64, stream, reps, symmetry=1)
+        paths["fp64_sym"] = {"ladder_launch_ms": ms,
+                             "ladders_solved_per_launch":
+                                 2 * (p0.n_om - (p0.n_om - 1) // 2) * orbit_count(p0.D, p0.nk),
+                             "effective_solves_per_s": 2 * p0.n_om * p0.N / (ms * 1e-3)}
+        for name, pr, ac in (("fp64_sym", B.DF_FP64, 0), ("adaptive_anderson_sym", B.DF_ADAPTIVE, ACCEL)):
+            conv = converge_each(B, problems, insts, ws, pr, stream, args.graph, accel=ac, symmetry=1)
+            paths.setdefault(name, {}).update(
+                {"s_per_converged_sigma": float(np.mean([c["seconds"] for c in conv])),
+                 "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
+                 "converged": conv})
+            log(f"{name}: {paths[name]['s_per_converged_sigma']:.3f} s per converged Sigma~")
         if not args.no_warm:
             sigma0, info = warm_start_leg(problems, args, log)
-            for name, pr, ac in (("warm_fp64", B.DF_FP64, 0), ("warm_adaptive", B.DF_ADAPTIVE, 0),
-                                 ("warm_adaptive_anderson", B.DF_ADAPTIVE, ACCEL)):
-                conv = converge_each(B, problems, insts, ws, pr, stream, args.graph, sigma0, accel=ac)
+            for name, pr, ac, sy in (("warm_fp64", B.DF_FP64, 0, 0), ("warm_adaptive", B.DF_ADAPTIVE, 0, 0),
+                                     ("warm_adaptive_anderson", B.DF_ADAPTIVE, ACCEL, 0),
+                                     ("warm_adaptive_anderson_sym", B.DF_ADAPTIVE, ACCEL, 1)):
+                conv = converge_each(B, problems, insts, ws, pr, stream, args.graph, sigma0, accel=ac,
+                                     symmetry=sy)
                 sec = float(np.mean([c["seconds"] for c in conv])) + info["inference_seconds_per_instance"]
                 paths[name] = {"s_per_converged_sigma": sec,
                                "mean_iterations": float(np.mean([c["iterations"] for c in conv])),

@@ -129,6 +129,17 @@ typedef struct {
  *               symmetries.  Same fixed point, fewer iterations.  The workspace
  *               grows by (2 accel + 3) n_nu N complex per instance: size it with
  *               the same options.
+ *   symmetry    0: every (c, Omega, q) ladder is solved.  1 (df_ladder_solve,
+ *               df_iterate): one q per orbit of the lattice point group (axis
+ *               permutations and reflections k_a -> -k_a) and Omega >= 0 only are
+ *               solved; the others are copied from them, conjugated with
+ *               nu -> -nu for Omega < 0 (2D 32x32: 153 of 1024 q, 16 of 31 Omega).
+ *               Valid when the inputs carry those symmetries - eps_k invariant
+ *               under the group, g(-nu) = g(nu)*, Delta(-nu) = Delta(nu)*,
+ *               gamma_{-Om}(-nu, -nu') = gamma_Om(nu, nu')* and a sigma (start value)
+ *               that is point-group invariant with Sigma~(-nu) = Sigma~(nu)* - as
+ *               those of the hypercubic Hubbard model are; the iteration keeps
+ *               them.  Results then equal those of symmetry 0 to rounding.
  */
 typedef struct {
     int32_t prec;
@@ -138,6 +149,7 @@ typedef struct {
     double switch_tol;
     int32_t use_graph;
     int32_t accel;
+    int32_t symmetry;
 } df_opts_t;
 
 /* Workspace bytes needed by any entry point for these instances and options. */

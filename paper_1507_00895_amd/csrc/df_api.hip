@@ -35,6 +35,9 @@ struct Shape {
     int D, nk, lognk, N, n_nu, n_om;
     int chunk_len, n_chunks;
     int items;                        // 2 n_om N ladder items
+    int im0;                          // bosonic index of Omega = 0
+    int n_irr;                        // point-group orbits of the q-grid
+    int items_sym;                    // 2 (n_om - im0) n_irr: symmetry-reduced ladder items
 };
 
 int check_inst(const df_inst_t &p, Shape *s) {
@@ -55,6 +58,10 @@ int check_inst(const df_inst_t &p, Shape *s) {
     s->n_nu = p.n_nu;
     s->n_om = p.n_om;
     s->items = 2 * p.n_om * (int)N;
+    s->im0 = (p.n_om - 1) / 2;
+    s->n_irr = 0;
+    for (int q = 0; q < (int)N; ++q) s->n_irr += (canonical_q(q, p.D, l) == q);
+    s->items_sym = 2 * (p.n_om - s->im0) * s->n_irr;
     int nch = (512 + p.n_nu - 1) / p.n_nu;
     if (nch > p.n_om) nch = p.n_om;
     if (nch < 1) nch = 1;
@@ -66,6 +73,7 @@ int check_inst(const df_inst_t &p, Shape *s) {
 // Per-instance workspace regions (byte offsets from the instance base).
 struct Layout {
     size_t gr, gdm, pdm, gtr, gp32, gtr32, part, norm, gd, chi, w;
+    size_t qrep, qlist;               // symmetry tables: int[N] each
     size_t fx, xh, rh, accpart;       // Anderson acceleration (0 when unused)
     size_t total;
 };
@@ -93,6 +101,8 @@ Layout layout_of(const Shape &s, int slots) {
     L.gd = take(fld);
     L.chi = take((size_t)s.n_om * fld);
     L.w = take(2 * (size_t)s.n_om * fld);
+    L.qrep = take((size_t)s.N * sizeof(int));
+    L.qlist = take((size_t)s.N * sizeof(int));
     L.fx = L.xh = L.rh = L.accpart = 0;
     if (slots > 0) {
         L.fx = take(fld);
@@ -361,11 +371,39 @@ int check_opts(const df_opts_t *o, bool need_loop, bool adaptive) {
     if (!o) return need_loop ? DF_E_INVAL : DF_OK;
     if (!ladder_prec(o->prec) && !(adaptive && o->prec == DF_ADAPTIVE)) return DF_E_INVAL;
     if (o->accel < 0 || o->accel > kAccMaxSlots - 1 || !isfinite(o->switch_tol)) return DF_E_INVAL;
+    if (o->symmetry != 0 && o->symmetry != 1) return DF_E_INVAL;
     if (need_loop) {
         if (!(o->mix > 0.0 && o->mix <= 1.0)) return DF_E_INVAL;
         if (o->max_iter < 1) return DF_E_INVAL;
         if (!isfinite(o->tol)) return DF_E_INVAL;
     }
+    return DF_OK;
+}
+
+// ---- symmetry reduction ---------------------------------------------------------
+int stage_sym_tables(const Shape &s, void *ws, size_t base, const Layout &L, hipStream_t st) {
+    SymTableArgs a{};
+    a.D = s.D;
+    a.lognk = s.lognk;
+    a.N = s.N;
+    a.qrep = at<int>(ws, base + L.qrep);
+    a.qlist = at<int>(ws, base + L.qlist);
+    HIPCHK(launch_sym_tables(a, st));
+    return DF_OK;
+}
+
+int stage_sym_expand(const Shape &s, void *ws, size_t base, const Layout &L, double *w,
+                     double *logdet, int8_t *status, hipStream_t st) {
+    SymExpandArgs a{};
+    a.n_nu = s.n_nu;
+    a.n_om = s.n_om;
+    a.N = s.N;
+    a.im0 = s.im0;
+    a.qrep = at<int>(ws, base + L.qrep);
+    a.w = w;
+    a.logdet = logdet;
+    a.status = status;
+    HIPCHK(launch_sym_expand(a, st));
     return DF_OK;
 }
 
@@ -387,7 +425,7 @@ struct Fused {
 // Group the active instances by ladder class and write the device table.
 // Ordinary (not captured) stream work, synchronised before returning.
 int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &act,
-                const std::vector<int> &prec, void *ws, Fused *F, hipStream_t st) {
+                const std::vector<int> &prec, bool sym, void *ws, Fused *F, hipStream_t st) {
     F->active.clear();
     F->cls.clear();
     F->table.clear();
@@ -425,7 +463,12 @@ int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &ac
             d.n_om = s.n_om;
             d.N = s.N;
             d.item0 = c.items;
-            c.items += s.items;
+            if (sym) {
+                d.qlist = at<int>(ws, b + L.qlist);
+                d.n_q = s.n_irr;
+                d.im0 = s.im0;
+            }
+            c.items += sym ? s.items_sym : s.items;
             c.n_nu = s.n_nu;
             c.variant = ladder_variant(s.n_nu, prec[i]);
             F->table.push_back(d);
@@ -477,6 +520,10 @@ int queue_fused_iteration(const df_inst_t *inst, const Plan &P, const Fused &F,
         double *gr = at<double>(ws, b + L.gr);
         double *part = at<double>(ws, b + L.part);
         double *w = inst[i].w ? inst[i].w : at<double>(ws, b + L.w);
+        if (o.symmetry) {
+            rc = stage_sym_expand(s, ws, b, L, w, inst[i].logdet, inst[i].status, st);
+            if (rc != DF_OK) return rc;
+        }
         rc = stage_sigma(inst[i], s, w, gr, part, st);
         if (rc != DF_OK) return rc;
         if (o.accel > 0) {
@@ -712,8 +759,21 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         a.N = s.N;
         a.item0 = 0;
         a.n_items = s.items;
+        const bool sym = opts && opts->symmetry;
+        if (sym) {
+            rc = stage_sym_tables(s, ws, b, L, st);
+            if (rc != DF_OK) return rc;
+            a.qlist = at<int>(ws, b + L.qlist);
+            a.n_q = s.n_irr;
+            a.im0 = s.im0;
+            a.n_items = s.items_sym;
+        }
         rc = launch_ladder_variant(ladder_variant(s.n_nu, prec), a, at<int>(ws, P.g.queue), ints, st);
         if (rc != DF_OK) return rc;
+        if (sym) {
+            rc = stage_sym_expand(s, ws, b, L, inst[i].w, inst[i].logdet, inst[i].status, st);
+            if (rc != DF_OK) return rc;
+        }
     }
     return DF_OK;
 }
@@ -770,6 +830,10 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     for (int i = 0; i < n_inst; ++i) {
         rc = stage_gamma_prep(inst[i], P.shape[i], ws, P.base[i], P.lay[i], st);
         if (rc != DF_OK) return rc;
+        if (opts->symmetry) {
+            rc = stage_sym_tables(P.shape[i], ws, P.base[i], P.lay[i], st);
+            if (rc != DF_OK) return rc;
+        }
     }
 
     hipGraphExec_t exec = nullptr;
@@ -796,7 +860,7 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     while (it < opts->max_iter && !act.empty()) {
         if (rebuild) {
             cleanup();
-            rc = build_fused(inst, P, act, cur, ws, &F, st);
+            rc = build_fused(inst, P, act, cur, opts->symmetry != 0, ws, &F, st);
             if (rc != DF_OK) return rc;
             if (graph) {
                 hipGraph_t g = nullptr;

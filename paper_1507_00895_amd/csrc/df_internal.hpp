@@ -89,6 +89,8 @@ struct LadderInst {
     int *count;                      // ladders outside the radius (atomic)
     int n_nu, n_om, N;
     int item0;                       // first global item of this instance
+    const int *qlist;                // symmetry-reduced launch (else null): solved q
+    int n_q, im0;                    // their count; first solved bosonic index
 };
 
 struct LadderArgs {
@@ -110,6 +112,8 @@ struct LadderArgs {
     int n_insts;                     // items are global; the fields above are resolved per item
     const float *gp32;               // FP32 ladder: (gamma, gamma_ij gamma_ji) pairs, FP32
     const float *gtr32;              // FP32 ladder: gamma transposed, FP32
+    const int *qlist;                // non-null: symmetry-reduced items (see item_coords)
+    int n_q, im0;
 };
 
 // Fused launches: find the instance of a global item, fill the per-instance
@@ -132,8 +136,63 @@ __device__ __forceinline__ int resolve_item(LadderArgs &a, int item) {
     a.n_nu = d.n_nu;
     a.n_om = d.n_om;
     a.N = d.N;
+    a.qlist = d.qlist;
+    a.n_q = d.n_q;
+    a.im0 = d.im0;
     return item - d.item0;
 }
+
+// An item's (c n_om + m index, q).  Full launches: items are (c, m, q), q
+// fastest.  Symmetry-reduced launches (qlist set): items are (c, m index >= im0,
+// k < n_q), k fastest, with q = qlist[k] - one q per point-group orbit and the
+// bosonic frequencies Omega >= 0; the others follow by symmetry (k_sym_expand).
+__device__ __forceinline__ void item_coords(const LadderArgs &a, int item, int *cm, int *q) {
+    if (!a.qlist) {
+        *q = item % a.N;
+        *cm = item / a.N;
+        return;
+    }
+    const int k = item % a.n_q, r = item / a.n_q;
+    const int nm = a.n_om - a.im0;
+    *q = a.qlist[k];
+    *cm = (r / nm) * a.n_om + a.im0 + r % nm;
+}
+
+// Representative of q's orbit under the point group of the hypercubic lattice
+// (axis permutations and k_a -> -k_a): per axis the smaller of c_a and nk - c_a,
+// sorted ascending from axis 0.  Host and device use this same function.
+__host__ __device__ inline int canonical_q(int q, int D, int lognk) {
+    const int nk = 1 << lognk;
+    int r[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+        const int c = (q >> (a * lognk)) & (nk - 1);
+        const int m = (nk - c) & (nk - 1);
+        r[a] = c < m ? c : m;
+    }
+    for (int i = 1; i < D; ++i)          // insertion sort of at most three values
+        for (int j = i; j > 0 && r[j - 1] > r[j]; --j) {
+            const int t = r[j];
+            r[j] = r[j - 1];
+            r[j - 1] = t;
+        }
+    int out = 0;
+    for (int a = 0; a < D; ++a) out |= r[a] << (a * lognk);
+    return out;
+}
+
+struct SymTableArgs {
+    int D, lognk, N;
+    int *qrep;                       // [N]: representative of each q
+    int *qlist;                      // [n_irr]: the representatives, ascending
+};
+
+struct SymExpandArgs {
+    int n_nu, n_om, N, im0;
+    const int *qrep;
+    double *w;                       // [2][n_om][n_nu][N]
+    double *logdet;                  // [2][n_om][N] or null
+    int8_t *status;                  // [2][n_om][N] or null
+};
 
 // Work-group b of a launch runs on XCD b % 8 (the dispatcher deals work-groups
 // round-robin over the eight XCDs, each with its own L2).  Give every XCD one
@@ -201,6 +260,8 @@ hipError_t launch_ladder_fp32(const LadderArgs &a, int occ, hipStream_t s);
 // pivoting kernel over a device-side queue of items (grid-stride, fixed grid)
 hipError_t launch_ladder_fp64_queue(const LadderArgs &a, int blocks, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);
+hipError_t launch_sym_tables(const SymTableArgs &a, hipStream_t s);
+hipError_t launch_sym_expand(const SymExpandArgs &a, hipStream_t s);
 hipError_t launch_lattice_fields(const LatticeFieldArgs &a, hipStream_t s);
 hipError_t launch_lattice_chi_ladder(const LatticeChiArgs &a, int items, hipStream_t s);
 hipError_t launch_lattice_chi_sum(const LatticeSumArgs &a, hipStream_t s);

@@ -60,8 +60,8 @@ __global__ __launch_bounds__(TR *TC) void k_ladder_fp64(LadderArgs a0) {
     const int item = resolve_item(a, a0.in_queue ? a0.in_queue[wi]
                                                   : a0.item0 + xcd_item(blockIdx.x, gridDim.x));
     const int n_nu = a.n_nu, N = a.N;
-    const int q = item % N;
-    const int cm = item / N;                 // c * n_om + m
+    int q, cm;
+    item_coords(a, item, &cm, &q);
     const int im = cm % a.n_om;
     const size_t nn = (size_t)n_nu * n_nu;
     const double *gam = a.gdm + 2 * (size_t)cm * nn;

@@ -33,8 +33,8 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
     const int gitem = a0.item0 + xcd_item(blockIdx.x, gridDim.x);   // global item (fused launches)
     const int item = resolve_item(a, gitem);
     const int n_nu = a.n_nu, N = a.N;
-    const int q = item % N;
-    const int cm = item / N;
+    int q, cm;
+    item_coords(a, item, &cm, &q);
     const int im = cm % a.n_om;
     const size_t nn = (size_t)n_nu * n_nu;
     const double *gam = a.gdm + 2 * (size_t)cm * nn;

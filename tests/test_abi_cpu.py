@@ -48,10 +48,10 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "df.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(df_inst_t), offsetof(df_inst_t, beta),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(df_inst_t), offsetof(df_inst_t, beta),
          offsetof(df_inst_t, g), offsetof(df_inst_t, status), sizeof(df_opts_t),
          offsetof(df_opts_t, max_iter), offsetof(df_opts_t, tol), offsetof(df_opts_t, switch_tol),
-         offsetof(df_opts_t, accel));
+         offsetof(df_opts_t, accel), offsetof(df_opts_t, symmetry));
   return 0;
 }
 ''')
@@ -61,7 +61,8 @@ int main(void) {
                                            check=True).stdout.split()]
     assert vals == [ctypes.sizeof(B.DfInst), B.DfInst.beta.offset, B.DfInst.g.offset,
                     B.DfInst.status.offset, ctypes.sizeof(B.DfOpts), B.DfOpts.max_iter.offset,
-                    B.DfOpts.tol.offset, B.DfOpts.switch_tol.offset, B.DfOpts.accel.offset]
+                    B.DfOpts.tol.offset, B.DfOpts.switch_tol.offset, B.DfOpts.accel.offset,
+                    B.DfOpts.symmetry.offset]
 
 
 def _inst(**kw):
@@ -110,6 +111,9 @@ def test_workspace_size_and_validation_order():
     assert lib.df_workspace_size(arr, 1, ctypes.byref(ad), ctypes.byref(n)) == B.DF_OK
     bad = B.make_opts(accel=9)
     assert lib.df_ladder_solve(arr, 1, ctypes.byref(bad), 0x1000, n.value, None) == B.DF_E_INVAL
+    bad = B.make_opts(symmetry=2)
+    assert lib.df_ladder_solve(arr, 1, ctypes.byref(bad), 0x1000, n.value, None) == B.DF_E_INVAL
+    assert lib.df_iterate(arr, 1, ctypes.byref(bad), None, None, 0x1000, n.value, None) == B.DF_E_INVAL
     # Anderson history needs workspace
     m0, m5 = ctypes.c_size_t(0), ctypes.c_size_t(0)
     assert lib.df_workspace_size(arr, 1, ctypes.byref(B.make_opts()), ctypes.byref(m0)) == B.DF_OK

@@ -1,0 +1,113 @@
+"""Symmetry-reduced ladder (opts.symmetry = 1): one q per point-group orbit and
+Omega >= 0 solved, the rest filled by symmetry.  Compared with the oracle's full
+ladder on the same chi~ (every (c, Omega, q), or a sample on large grids), and
+the reduced loop with the plain one.
+"""
+import numpy as np
+import pytest
+
+from oracle import df_oracle as O
+from paper_1507_00895_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-9, 2: 2e-5}
+
+
+def rel(x, ref):
+    den = np.abs(ref).max()
+    return float(np.abs(x - ref).max() / den)
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1507_00895_amd import binding
+    binding.load()
+    return binding
+
+
+# (D, nk, n_nu, n_om, beta, U, t)
+SHAPES = [
+    (2, 8, 16, 5, 10.0, 2.0, 0.1),
+    (1, 64, 20, 7, 10.0, 2.0, 0.1),      # ragged n_nu, D = 1 (reflections only)
+    (3, 8, 16, 7, 15.0, 3.0, 0.182358),  # O_h: 48 elements
+    (2, 16, 48, 9, 10.0, 2.0, 0.1),
+    (2, 32, 64, 31, 20.0, 2.0, 0.1),     # the bench shape (sampled q)
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "D{}nk{}nu{}om{}".format(*s[:4]))
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_reduced_ladder_matches_full_oracle(B, shape, prec):
+    import torch
+    D, nk, n_nu, n_om, beta, U, t = shape
+    p = I.atomic_limit_problem(D, nk, n_nu, n_om, beta, U, t)
+    x = B.make_instance(p)
+    ws = B.workspace([x])
+    print(f"symmetry ladder {shape} prec {prec}", flush=True)
+    B.df_dual_gf([x], ws)
+    B.df_bubble([x], ws)
+    x.w.fill_(float("nan"))
+    x.logdet.fill_(float("nan"))
+    x.status.fill_(-1)
+    B.df_ladder_solve([x], ws, B.make_opts(prec=prec, symmetry=1))
+    torch.cuda.synchronize()
+    chi = x.chi.cpu().numpy()
+    gam = O.spin_channels(p.gamma_uu, p.gamma_ud)
+    N = p.N
+    if 2 * n_om * N * n_nu ** 3 <= 3e8:
+        qs = np.arange(N)
+    else:
+        rng = np.random.default_rng(11)
+        qs = np.unique(np.concatenate([[0, N - 1], rng.choice(N, 60, replace=False)]))
+    lr = O.ladder(gam, chi[:, :, qs])
+    W = x.w.cpu().numpy()
+    assert np.isfinite(W).all()
+    assert np.array_equal(x.status.cpu().numpy()[:, :, qs], lr.status)
+    assert rel(W[..., qs], lr.W) <= TOL[prec]
+    ld = x.logdet.cpu().numpy()[:, :, qs]
+    tol_ld = 1e-11 if prec == 0 else 1e-4
+    assert np.abs(ld.real - lr.logdet.real).max() <= tol_ld
+    assert np.abs(np.exp(1j * ld.imag) - np.exp(1j * lr.logdet.imag)).max() <= tol_ld
+
+
+@pytest.mark.parametrize("graph,accel,prec", [(0, 0, 0), (1, 0, 0), (1, 5, 0), (1, 5, 3)])
+def test_reduced_loop_equals_plain_loop(B, graph, accel, prec):
+    import torch
+    p = I.atomic_limit_problem(2, 16, 32, 7, 10.0, 2.0, 0.1)
+    out = []
+    for sym in (0, 1):
+        x = B.make_instance(p)
+        ws = B.workspace([x], B.make_opts(accel=accel))
+        s = torch.cuda.Stream()
+        code, it, d = B.df_iterate([x], ws, B.make_opts(prec=prec, mix=0.5, tol=1e-10, max_iter=300,
+                                                         use_graph=graph, accel=accel,
+                                                         symmetry=sym),
+                                   stream=s.cuda_stream, allow=(B.DF_OK, B.DF_W_FALLBACK))
+        s.synchronize()
+        out.append((x.sigma.cpu().numpy(), it, d[0]))
+    assert out[1][2] < 1e-10
+    assert abs(out[0][1] - out[1][1]) <= 1
+    assert rel(out[1][0], out[0][0]) <= 1e-9
+
+
+def test_reduced_fused_instances(B):
+    """Three instances of two shapes in one reduced loop, against each alone (plain)."""
+    import torch
+    probs = [I.atomic_limit_problem(2, 8, 16, 5, 10.0, U, 0.1) for U in (1.0, 2.0)] + \
+            [I.atomic_limit_problem(3, 4, 16, 3, 8.0, 2.0, 0.12)]
+    xs = [B.make_instance(q) for q in probs]
+    ws = B.workspace(xs)
+    B.df_iterate(xs, ws, B.make_opts(mix=0.5, tol=0.0, max_iter=8, use_graph=1, symmetry=1),
+                 stream=torch.cuda.current_stream().cuda_stream, allow=(B.DF_OK, B.DF_W_FALLBACK))
+    torch.cuda.synchronize()
+    for q, x in zip(probs, xs):
+        y = B.make_instance(q)
+        wy = B.workspace([y])
+        B.df_iterate([y], wy, B.make_opts(mix=0.5, tol=0.0, max_iter=8),
+                     allow=(B.DF_OK, B.DF_W_FALLBACK))
+        torch.cuda.synchronize()
+        assert rel(x.sigma.cpu().numpy(), y.sigma.cpu().numpy()) <= 1e-11
+        assert rel(x.w.cpu().numpy(), y.w.cpu().numpy()) <= 1e-11
