@@ -78,7 +78,7 @@ typedef void *df_stream_t;      /* hipStream_t; NULL is the null stream */
 
 /*
  * One problem instance.
- *   D      lattice dimension, 1..3
+ *   D      lattice dimension, 1..4 (the hypercubic lattices of the paper)
  *   nk     k-points per axis, a power of two in [4, 64]; N = nk^D <= 4096
  *   n_nu   fermionic frequencies, even, 2..128
  *   n_om   bosonic frequencies, odd, 1 <= n_om <= n_nu - 1

@@ -41,7 +41,7 @@ struct Shape {
 };
 
 int check_inst(const df_inst_t &p, Shape *s) {
-    if (p.D < 1 || p.D > 3) return DF_E_UNSUPPORTED;
+    if (p.D < 1 || p.D > 4) return DF_E_UNSUPPORTED;
     const int l = ilog2_exact(p.nk);
     if (l < 2 || l > 6) return DF_E_UNSUPPORTED;
     long N = 1;
@@ -658,7 +658,7 @@ const char *df_strerror(int code) {
     switch (code) {
         case DF_OK: return "success";
         case DF_E_INVAL: return "invalid argument";
-        case DF_E_UNSUPPORTED: return "unsupported shape (D in 1..3, nk power of two in [4,64], nk^D <= 4096, n_nu <= 128)";
+        case DF_E_UNSUPPORTED: return "unsupported shape (D in 1..4, nk power of two in [4,64], nk^D <= 4096, n_nu <= 128)";
         case DF_E_WORKSPACE: return "workspace missing, misaligned (256 B) or too small";
         case DF_E_HIP: return "HIP runtime error";
         case DF_E_NONFINITE: return "dual self-energy became non-finite";

@@ -163,13 +163,13 @@ __device__ __forceinline__ void item_coords(const LadderArgs &a, int item, int *
 // sorted ascending from axis 0.  Host and device use this same function.
 __host__ __device__ inline int canonical_q(int q, int D, int lognk) {
     const int nk = 1 << lognk;
-    int r[3] = {0, 0, 0};
+    int r[4] = {0, 0, 0, 0};
     for (int a = 0; a < D; ++a) {
         const int c = (q >> (a * lognk)) & (nk - 1);
         const int m = (nk - c) & (nk - 1);
         r[a] = c < m ? c : m;
     }
-    for (int i = 1; i < D; ++i)          // insertion sort of at most three values
+    for (int i = 1; i < D; ++i)          // insertion sort of at most four values
         for (int j = i; j > 0 && r[j - 1] > r[j]; --j) {
             const int t = r[j];
             r[j] = r[j - 1];

@@ -78,8 +78,10 @@ def _inst(**kw):
     (dict(n_nu=15), B.DF_E_INVAL),           # odd fermionic count
     (dict(n_om=17), B.DF_E_INVAL),           # n_om > n_nu - 1
     (dict(nk=12), B.DF_E_UNSUPPORTED),       # not a power of two
-    (dict(D=4), B.DF_E_UNSUPPORTED),
+    (dict(D=5, nk=4), B.DF_E_UNSUPPORTED),
+    (dict(D=0), B.DF_E_UNSUPPORTED),
     (dict(D=3, nk=32), B.DF_E_UNSUPPORTED),  # N = 32768 > 4096
+    (dict(D=4, nk=16), B.DF_E_UNSUPPORTED),  # N = 65536 > 4096
     (dict(n_nu=130, n_om=3), B.DF_E_UNSUPPORTED),
     (dict(beta=0.0), B.DF_E_INVAL),
 ])

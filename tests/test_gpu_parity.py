@@ -47,6 +47,8 @@ SHAPES = [
     (3, 16, 96, 3, 15.0, 3.0, I.T_REMAP_3D),
     (2, 16, 128, 3, 10.0, 2.0, 0.1),
     (2, 64, 32, 3, 10.0, 2.0, 0.1),     # largest 2D grid
+    (4, 4, 16, 3, 8.0, 2.0, 0.1),       # 4D hypercubic lattice
+    (4, 8, 16, 1, 10.0, 2.0, 0.1),      # largest 4D grid (N = 4096)
 ]
 
 
@@ -120,12 +122,12 @@ def test_iterate_small_workload_ten_iterations(torch_dev):
     assert abs(diffs[0] - r.diff) <= 1e-10 * r.diff
 
 
-@pytest.mark.parametrize("use_graph", [0, 1])
-def test_iterate_converges_like_oracle(torch_dev, use_graph):
-    """3D 4^3 lattice, several Omega: run both sides to tol 1e-11."""
+@pytest.mark.parametrize("use_graph,D", [(0, 3), (1, 3), (1, 4)])
+def test_iterate_converges_like_oracle(torch_dev, use_graph, D):
+    """3D 4^3 and 4D 4^4 lattices, several Omega: run both sides to tol 1e-11."""
     torch = torch_dev
     from paper_1507_00895_amd import binding as B
-    p = I.atomic_limit_problem(3, 4, 16, 5, 8.0, 2.0, 0.12)
+    p = I.atomic_limit_problem(D, 4, 16, 5, 8.0, 2.0, 0.12 if D == 3 else 0.1)
     inst = B.make_instance(p)
     ws = B.workspace([inst])
     torch.cuda.synchronize()

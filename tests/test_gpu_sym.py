@@ -35,6 +35,7 @@ SHAPES = [
     (3, 8, 16, 7, 15.0, 3.0, 0.182358),  # O_h: 48 elements
     (2, 16, 48, 9, 10.0, 2.0, 0.1),
     (2, 32, 64, 31, 20.0, 2.0, 0.1),     # the bench shape (sampled q)
+    (4, 4, 16, 5, 8.0, 2.0, 0.1),        # 4D: 384 group elements
 ]
 
 

@@ -129,7 +129,7 @@ def _brute_bubble(G, D, nk, n_om, beta):
     return out
 
 
-@pytest.mark.parametrize("D,nk", [(2, 4), (2, 6), (3, 4), (1, 8)])
+@pytest.mark.parametrize("D,nk", [(2, 4), (2, 6), (3, 4), (1, 8), (4, 4)])
 def test_p4_bubble_fft_and_direct_match_brute_force(D, nk):
     N = nk ** D
     G = I.random_complex((4, N), seed=10 + D * nk)
