@@ -1,0 +1,120 @@
+"""The paper's convergence and cost sweeps (Sec. 4, "Example I and performance
+analysis") on the GPU path.
+
+The 2D Hubbard model with the closed-form atomic-limit inputs at U = 20,
+mu = U/2, beta = 1 (t = 1) is converged with df_iterate for a range of one
+control parameter x while the others stay at the paper's values:
+
+  om   N_Omega (bosonic frequencies)  at N_omega = 48, N_k = 16
+  nu   N_omega (fermionic window)     at N_Omega = 3,  N_k = 8
+  k    N_k (k-points per axis)        at N_Omega = 3,  N_omega = 48
+
+For each point it records the wall time to convergence (tol 1e-10) and
+g = G~(i pi / beta, k = 0), and reports delta_g = |g_x - g_inf| / |g_inf|, with
+g_inf from a fit g_x = g_inf + a x^-p over the largest points of the sweep
+(the paper extrapolates N_x -> infinity the same way, eq. deltag).
+
+    python -m paper_1507_00895_amd.experiments --sweep om|nu|k|all [--repeat R]
+
+prints one JSON object per sweep.  Every step runs in libdf's kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+U, BETA, T_HOP = 20.0, 1.0, 1.0
+
+SWEEPS = {
+    "om": dict(param="n_om", values=[1, 3, 5, 7, 9, 13, 17, 23, 31, 39, 47], n_nu=48, nk=16, n_om=None),
+    "nu": dict(param="n_nu", values=[8, 12, 16, 24, 32, 48, 64, 96, 128], n_nu=None, nk=8, n_om=3),
+    "k": dict(param="nk", values=[4, 8, 16, 32, 64], n_nu=48, nk=None, n_om=3),
+}
+
+
+def converge_point(B, inputs, D, nk, n_nu, n_om, repeat=3, tol=1e-10):
+    """Converge one point; returns (best wall seconds, g = G~(i pi/beta, k=0), iterations,
+    whether tol was reached)."""
+    import torch
+    p = inputs.atomic_limit_problem(D, nk, n_nu, n_om, BETA, U, T_HOP)
+    x = B.make_instance(p)
+    opts = B.make_opts(mix=0.5, tol=tol, max_iter=500, use_graph=1)
+    ws = B.workspace([x], opts)
+    stream = torch.cuda.Stream()
+    best, it, code = None, 0, 0
+    for _ in range(repeat):
+        x.sigma.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, it, d = B.df_iterate([x], ws, opts, stream=stream.cuda_stream,
+                                   allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    n0 = n_nu // 2                                   # nu_n0 = pi / beta
+    g = complex(x.gd[n0, 0].item())
+    return best, g, it, code != B.DF_E_NOT_CONVERGED
+
+
+def extrapolate(xs, gs, tail=4):
+    """g_inf of the fit g = g_inf + a x^-p on the last `tail` points (real and
+    imaginary parts share p); falls back to the last value when the fit fails."""
+    from scipy.optimize import least_squares
+    xs = np.asarray(xs[-tail:], float)
+    gs = np.asarray(gs[-tail:], complex)
+
+    def res(v):
+        ginf = v[0] + 1j * v[1]
+        a = v[2] + 1j * v[3]
+        r = gs - (ginf + a * xs ** (-v[4]))
+        return np.concatenate([r.real, r.imag]) / np.abs(gs).max()
+
+    v0 = [gs[-1].real, gs[-1].imag, 0.0, 0.0, 1.0]
+    try:
+        sol = least_squares(res, v0, bounds=([-np.inf] * 4 + [0.05], [np.inf] * 4 + [8.0]))
+        return complex(sol.x[0], sol.x[1]), float(sol.x[4])
+    except Exception:
+        return complex(gs[-1]), None
+
+
+def run_sweep(name, repeat=3):
+    from paper_1507_00895_amd import binding as B
+    from paper_1507_00895_amd import inputs
+    cfg = SWEEPS[name]
+    rows = []
+    for v in cfg["values"]:
+        kw = dict(nk=cfg["nk"], n_nu=cfg["n_nu"], n_om=cfg["n_om"])
+        kw[cfg["param"]] = v
+        sec, g, it, ok = converge_point(B, inputs, 2, kw["nk"], kw["n_nu"], kw["n_om"], repeat)
+        rows.append({cfg["param"]: v, "seconds": sec, "iterations": it, "converged": ok,
+                     "g": [g.real, g.imag]})
+        print(f"[experiments] {name} {cfg['param']}={v}: {sec * 1e3:.2f} ms, {it} iterations",
+              file=sys.stderr, flush=True)
+    xs = [r[cfg["param"]] for r in rows]
+    gs = [complex(*r["g"]) for r in rows]
+    ginf, power = extrapolate(xs, gs)
+    for r, g in zip(rows, gs):
+        r["delta_g"] = abs(g - ginf) / abs(ginf)
+    return {"sweep": name, "fixed": {k: cfg[k] for k in ("n_nu", "nk", "n_om") if cfg[k] is not None},
+            "U": U, "beta": BETA, "t": T_HOP, "tol": 1e-10, "g_inf": [ginf.real, ginf.imag],
+            "fit_power": power, "points": rows}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sweep", choices=["om", "nu", "k", "all"], default="all")
+    ap.add_argument("--repeat", type=int, default=3)
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available(), "the sweeps run on the GPU path"
+    names = ["om", "nu", "k"] if args.sweep == "all" else [args.sweep]
+    for n in names:
+        print(json.dumps(run_sweep(n, args.repeat)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

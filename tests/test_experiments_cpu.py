@@ -1,0 +1,23 @@
+"""Host-side part of the scaling sweeps: the N_x -> infinity extrapolation."""
+import numpy as np
+
+from paper_1507_00895_amd import experiments as E
+
+
+def test_extrapolation_recovers_the_limit_of_a_power_law():
+    xs = np.array([8, 12, 16, 24, 32, 48, 64, 96, 128], float)
+    ginf, a, p = 0.031 - 0.27j, 0.8 + 0.3j, 1.7
+    gs = ginf + a * xs ** (-p)
+    got, power = E.extrapolate(list(xs), list(gs))
+    assert abs(got - ginf) <= 1e-8 * abs(ginf)
+    assert abs(power - p) <= 1e-6
+
+
+def test_sweep_points_respect_the_library_limits():
+    for cfg in E.SWEEPS.values():
+        for v in cfg["values"]:
+            kw = dict(nk=cfg["nk"], n_nu=cfg["n_nu"], n_om=cfg["n_om"])
+            kw[cfg["param"]] = v
+            assert kw["n_nu"] % 2 == 0 and 2 <= kw["n_nu"] <= 128
+            assert kw["n_om"] % 2 == 1 and kw["n_om"] <= kw["n_nu"] - 1
+            assert kw["nk"] in (4, 8, 16, 32, 64)
