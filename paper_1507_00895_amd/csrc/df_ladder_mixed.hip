@@ -31,7 +31,10 @@ constexpr double CERT_MAX_MIXED = 0.99;
 template <int NP> struct MixedShared {
     union {
         GjShared<float, NP> gj;          // during the FP32 sweep
-        cf Tw[NP / 16][16][17];          // Z0 = X gamma: per-wave exchange of X tiles
+        struct {
+            cf Tw[NP / 16][16][17];      // per-wave exchange of X tiles
+            cf Gs[2][16][NP];            // gamma rows of the current / next 16-row block
+        } z0;                            // during Z0 = X gamma
         cf Zs[NP][NP];                   // then Z0 (FP32), all rows; later E
     };
 };
@@ -241,50 +244,49 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             Zr[tc] = f4{0, 0, 0, 0};
             Zi[tc] = f4{0, 0, 0, 0};
         }
-        // k = 4 s + lg; gamma rows of step s + 1 are requested once those of
-        // step s have arrived (the same pipelining as the residual below)
-        fv4 gv_nx[NT];
-        {
-            int k = lg;
-            asm volatile("" : "+v"(k));
+        // gamma goes through LDS one 16-row block at a time, loaded once for
+        // the four waves (FP32 pairs of the vertex copy, padding zeroed); the
+        // next block is in flight while this one's products run
+        fv4 gpre[4];
+        auto load_block = [&](int kt) {
 #pragma unroll
-            for (int tc = 0; tc < NT; ++tc)
-                gv_nx[tc] = ld4f(gp, (size_t)min(k, nm1) * n_nu + min(16 * tc + lj, nm1));
-        }
+            for (int i = 0; i < 4; ++i) {
+                const int e = tid + i * NP * 4, r = e / NP, c = e % NP;
+                gpre[i] = ld4f(gp, (size_t)min(16 * kt + r, nm1) * n_nu + min(c, nm1));
+            }
+        };
+        auto store_block = [&](int kt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = tid + i * NP * 4, r = e / NP, c = e % NP;
+                const bool in = (16 * kt + r < n_nu) && (c < n_nu);
+                sh.z0.Gs[kt & 1][r][c] = in ? cf{gpre[i].x, gpre[i].y} : cf{0.f, 0.f};
+            }
+        };
+        load_block(0);
+        store_block(0);
+        __syncthreads();
 #pragma unroll
         for (int kt = 0; kt < NT; ++kt) {
+            if (kt + 1 < NT) load_block(kt + 1);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                sh.Tw[w][MT<float>::row(lg, r)][lj] = cf{Cr[kt][r], Ci[kt][r]};
+                sh.z0.Tw[w][MT<float>::row(lg, r)][lj] = cf{Cr[kt][r], Ci[kt][r]};
             wave_sync_lds();
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
-                const int st_ = 4 * kt + k4;
-                const int k = 4 * st_ + lg;
-                fv4 gv[NT];
-#pragma unroll
-                for (int tc = 0; tc < NT; ++tc) gv[tc] = gv_nx[tc];
-                __builtin_amdgcn_sched_barrier(0);
-                if (st_ + 1 < 4 * NT) {
-                    int kn = k + 4;
-                    asm volatile("" : "+v"(kn) : "v"(gv[0].x));
-#pragma unroll
-                    for (int tc = 0; tc < NT; ++tc)
-                        gv_nx[tc] = ld4f(gp, (size_t)min(kn, nm1) * n_nu + min(16 * tc + lj, nm1));
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                const cf xa = sh.Tw[w][lj][4 * k4 + lg];
+                const cf xa = sh.z0.Tw[w][lj][4 * k4 + lg];
 #pragma unroll
                 for (int tc = 0; tc < NT; ++tc) {
-                    const bool in = (k < n_nu) && (16 * tc + lj < n_nu);
-                    const float br = in ? gv[tc].x : 0.f, bi = in ? gv[tc].y : 0.f;
-                    Zr[tc] = MT<float>::mma(xa.re, br, Zr[tc]);
-                    Zr[tc] = MT<float>::mma_na(xa.im, bi, Zr[tc]);
-                    Zi[tc] = MT<float>::mma(xa.re, bi, Zi[tc]);
-                    Zi[tc] = MT<float>::mma(xa.im, br, Zi[tc]);
+                    const cf b = sh.z0.Gs[kt & 1][4 * k4 + lg][16 * tc + lj];
+                    Zr[tc] = MT<float>::mma(xa.re, b.re, Zr[tc]);
+                    Zr[tc] = MT<float>::mma_na(xa.im, b.im, Zr[tc]);
+                    Zi[tc] = MT<float>::mma(xa.re, b.im, Zi[tc]);
+                    Zi[tc] = MT<float>::mma(xa.im, b.re, Zi[tc]);
                 }
             }
-            wave_sync_lds();   // the slot is rewritten by the next tile
+            if (kt + 1 < NT) store_block(kt + 1);
+            __syncthreads();   // the next block is in place; this one and the slot are free
         }
         __syncthreads();   // Zs overlays the exchange slots
         // ---- share Z0 (the registers are free again once it is in LDS)
