@@ -11,8 +11,9 @@ control parameter x while the others stay at the paper's values:
 
 For each point it records the wall time to convergence (tol 1e-10) and
 g = G~(i pi / beta, k = 0), and reports delta_g = |g_x - g_inf| / |g_inf|, with
-g_inf from a fit g_x = g_inf + a x^-p over the largest points of the sweep
-(the paper extrapolates N_x -> infinity the same way, eq. deltag).
+g_inf from a fit g_x = g_inf + a x^-p over the five largest points of the
+sweep (the paper extrapolates N_x -> infinity, eq. deltag, without saying
+how; a power law is what its Figs. 2-3 show).
 
     python -m paper_1507_00895_amd.experiments --sweep om|nu|k|all [--repeat R]
 
@@ -60,25 +61,33 @@ def converge_point(B, inputs, D, nk, n_nu, n_om, repeat=3, tol=1e-10):
     return best, g, it, code != B.DF_E_NOT_CONVERGED
 
 
-def extrapolate(xs, gs, tail=4):
-    """g_inf of the fit g = g_inf + a x^-p on the last `tail` points (real and
-    imaginary parts share p); falls back to the last value when the fit fails."""
-    from scipy.optimize import least_squares
+def extrapolate(xs, gs, tail=5):
+    """g_inf of the fit g = g_inf + a x^-p on the last `tail` points.  For a fixed p
+    the model is linear in (g_inf, a): those come from least squares, and p from
+    the smallest residual over a grid refined twice (variable projection).
+    Returns (g_inf, p); (last g, None) when the last two points already agree
+    to rounding (exponential convergence, as in N_k) or there are too few."""
     xs = np.asarray(xs[-tail:], float)
     gs = np.asarray(gs[-tail:], complex)
+    if len(xs) < 3 or abs(gs[-1] - gs[-2]) <= 1e-13 * abs(gs[-1]):
+        return complex(gs[-1]), None   # converged to rounding: nothing to extrapolate
 
-    def res(v):
-        ginf = v[0] + 1j * v[1]
-        a = v[2] + 1j * v[3]
-        r = gs - (ginf + a * xs ** (-v[4]))
-        return np.concatenate([r.real, r.imag]) / np.abs(gs).max()
+    def fit(p):
+        A = np.stack([np.ones_like(xs), xs ** (-p)], axis=1).astype(complex)
+        c, *_ = np.linalg.lstsq(A, gs, rcond=None)
+        return c, float(np.linalg.norm(A @ c - gs))
 
-    v0 = [gs[-1].real, gs[-1].imag, 0.0, 0.0, 1.0]
-    try:
-        sol = least_squares(res, v0, bounds=([-np.inf] * 4 + [0.05], [np.inf] * 4 + [8.0]))
-        return complex(sol.x[0], sol.x[1]), float(sol.x[4])
-    except Exception:
-        return complex(gs[-1]), None
+    lo, hi = 0.05, 8.0
+    best = None
+    for _ in range(3):
+        grid = np.linspace(lo, hi, 401)
+        res = [fit(p)[1] for p in grid]
+        i = int(np.argmin(res))
+        best = grid[i]
+        step = grid[1] - grid[0]
+        lo, hi = max(0.05, best - 2 * step), min(8.0, best + 2 * step)
+    c, _ = fit(best)
+    return complex(c[0]), float(best)
 
 
 def run_sweep(name, repeat=3):

@@ -21,3 +21,9 @@ def test_sweep_points_respect_the_library_limits():
             assert kw["n_nu"] % 2 == 0 and 2 <= kw["n_nu"] <= 128
             assert kw["n_om"] % 2 == 1 and kw["n_om"] <= kw["n_nu"] - 1
             assert kw["nk"] in (4, 8, 16, 32, 64)
+
+
+def test_extrapolation_of_a_converged_sweep_is_its_last_value():
+    g = [0.3 + 0.1j, 0.30001 + 0.1j, 0.3000100000001 + 0.1j, 0.30001 + 0.1j, 0.30001 + 0.1j]
+    got, power = E.extrapolate([4, 8, 16, 32, 64], g)
+    assert got == g[-1] and power is None
