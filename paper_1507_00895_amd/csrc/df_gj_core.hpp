@@ -380,43 +380,43 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
         }
         __syncthreads();
 
-        T gr[4], gim[4];
-        if (w == t) {
+        if constexpr (sizeof(T) == 4) {
+            T gr[4], gim[4];
+            if (w == t) {
 #pragma unroll
-            for (int k4 = 0; k4 < 4; ++k4) {
-                ct g = sh.Xw[t][lj][4 * k4 + lg];
-                if (lj == 4 * k4 + lg) g.re -= T(1);
-                gr[k4] = g.re;
-                gim[k4] = g.im;
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    ct g = sh.Xw[t][lj][4 * k4 + lg];
+                    if (lj == 4 * k4 + lg) g.re -= T(1);
+                    gr[k4] = g.re;
+                    gim[k4] = g.im;
+                }
+            } else {
+                v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    const ct xa = sh.Xw[w][lj][4 * k4 + lg];
+                    const ct b = sh.Xw[t][4 * k4 + lg][lj];
+                    Gr = MT<T>::mma_na(xa.re, b.re, Gr);
+                    Gr = MT<T>::mma(xa.im, b.im, Gr);
+                    Gi = MT<T>::mma_na(xa.re, b.im, Gi);
+                    Gi = MT<T>::mma_na(xa.im, b.re, Gi);
+                }
+                Cr[0] = Gr;
+                Ci[0] = Gi;
+                wave_sync_lds();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Gr[r], Gi[r]};
+                wave_sync_lds();
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+                    const ct g = sh.Xw[w][lj][4 * k4 + lg];
+                    gr[k4] = g.re;
+                    gim[k4] = g.im;
+                }
             }
-        } else {
-            v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};
 #pragma unroll
-            for (int k4 = 0; k4 < 4; ++k4) {
-                const ct xa = sh.Xw[w][lj][4 * k4 + lg];
-                const ct b = sh.Xw[t][4 * k4 + lg][lj];
-                Gr = MT<T>::mma_na(xa.re, b.re, Gr);
-                Gr = MT<T>::mma(xa.im, b.im, Gr);
-                Gi = MT<T>::mma_na(xa.re, b.im, Gi);
-                Gi = MT<T>::mma_na(xa.im, b.re, Gi);
-            }
-            Cr[0] = Gr;
-            Ci[0] = Gi;
-            wave_sync_lds();
-#pragma unroll
-            for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Gr[r], Gi[r]};
-            wave_sync_lds();
-#pragma unroll
-            for (int k4 = 0; k4 < 4; ++k4) {
-                const ct g = sh.Xw[w][lj][4 * k4 + lg];
-                gr[k4] = g.re;
-                gim[k4] = g.im;
-            }
-        }
-#pragma unroll
-        for (int p = 1; p < NT; ++p) {
-            const int c = (p + t) % NT;
-            if constexpr (sizeof(T) == 4) {
+            for (int p = 1; p < NT; ++p) {
+                const int c = (p + t) % NT;
                 // three real products per complex one (3M form): T1 = G_re B_re,
                 // T2 = G_im B_im, Ci += (G_re + G_im)(B_re + B_im) - T1 - T2.
                 // In FP32 the extra accumulators fit the register budget and
@@ -432,14 +432,42 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
                 }
                 Cr[p] += T1 - T2;
                 Ci[p] -= T1 + T2;
-            } else {
+            }
+        } else {
+            // G_w in LDS (this wave's exchange slot): the inverse for w = t (its
+            // diagonal minus one below), -A_wt A_tt^-1 formed here for the others
+            if (w != t) {
+                v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
+                    const ct xa = sh.Xw[w][lj][4 * k4 + lg];
+                    const ct b = sh.Xw[t][4 * k4 + lg][lj];
+                    Gr = MT<T>::mma_na(xa.re, b.re, Gr);
+                    Gr = MT<T>::mma(xa.im, b.im, Gr);
+                    Gi = MT<T>::mma_na(xa.re, b.im, Gi);
+                    Gi = MT<T>::mma_na(xa.im, b.re, Gi);
+                }
+                Cr[0] = Gr;
+                Ci[0] = Gi;
+                wave_sync_lds();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Gr[r], Gi[r]};
+                wave_sync_lds();
+            }
+            // FP64: the A operand comes from LDS one k-slice at a time, used
+            // across the tiles, so no copy of G is held through the update
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) {
+                ct g = sh.Xw[w][lj][4 * k4 + lg];
+                if (w == t && lj == 4 * k4 + lg) g.re -= T(1);
+#pragma unroll
+                for (int p = 1; p < NT; ++p) {
+                    const int c = (p + t) % NT;
                     const ct b = sh.Rb[4 * k4 + lg][16 * c + lj];
-                    Cr[p] = MT<T>::mma(gr[k4], b.re, Cr[p]);
-                    Cr[p] = MT<T>::mma_na(gim[k4], b.im, Cr[p]);
-                    Ci[p] = MT<T>::mma(gr[k4], b.im, Ci[p]);
-                    Ci[p] = MT<T>::mma(gim[k4], b.re, Ci[p]);
+                    Cr[p] = MT<T>::mma(g.re, b.re, Cr[p]);
+                    Cr[p] = MT<T>::mma_na(g.im, b.im, Cr[p]);
+                    Ci[p] = MT<T>::mma(g.re, b.im, Ci[p]);
+                    Ci[p] = MT<T>::mma(g.im, b.re, Ci[p]);
                 }
             }
         }

@@ -154,7 +154,9 @@ __device__ __forceinline__ void item_coords(const LadderArgs &a, int item, int *
     }
     const int k = item % a.n_q, r = item / a.n_q;
     const int nm = a.n_om - a.im0;
-    *q = a.qlist[k];
+    // the work-group's q is uniform: keep it (and every address built from it)
+    // in scalar registers, as in the full launches
+    *q = __builtin_amdgcn_readfirstlane(a.qlist[k]);
     *cm = (r / nm) * a.n_om + a.im0 + r % nm;
 }
 
