@@ -187,11 +187,13 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
 
 /* Autotuner for the batched ladder (the hot step of every iteration).  For each
  * distinct n_nu among the instances (with opts->prec; opts may be NULL =
- * DF_FP64; DF_ADAPTIVE tunes both of its precisions) it builds that instance's ladder inputs in the workspace (G~ from
- * sigma, NULL = zero, and chi), times every ladder kernel variant able to run
- * them (three launches after an untimed one, HIP events on the stream, two
- * rounds over the candidates, each variant keeping its faster round), and
- * keeps the fastest for later calls of this process.  When the environment
+ * DF_FP64; DF_ADAPTIVE tunes both of its precisions) it builds the ladder
+ * inputs of all instances with that n_nu in the workspace (G~ from sigma,
+ * NULL = zero, and chi), times every ladder kernel variant able to run them on
+ * one fused launch over those instances - the launch df_iterate makes - (three
+ * launches after an untimed one, HIP events on the stream, two rounds over the
+ * candidates, each variant keeping its faster round), and keeps the fastest
+ * for later calls of this process.  When the environment
  * variable DF_TUNE_CACHE names a file, choices are read from it on first use
  * and the whole table is written back here.  Every variant gives results of
  * the same precision class (bit patterns may differ between variants).

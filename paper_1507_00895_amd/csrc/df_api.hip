@@ -1041,37 +1041,59 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         if (e0) (void)hipEventDestroy(e0);
         return DF_E_HIP;
     }
+    // One group per distinct n_nu: every instance of the group gets its ladder
+    // inputs in the workspace (G~ from sigma, NULL = zero, and chi), and the
+    // variants are timed on one fused launch over the whole group - the launch
+    // df_iterate makes - writing only workspace outputs.
     std::vector<int> done;
-    for (int i = 0; i < n_inst && rc == DF_OK; ++i) {
-        const Shape &s = P.shape[i];
+    for (int i0 = 0; i0 < n_inst && rc == DF_OK; ++i0) {
+        const int n_nu = P.shape[i0].n_nu;
         bool seen = false;
-        for (int n : done) seen = seen || (n == s.n_nu);
+        for (int n : done) seen = seen || (n == n_nu);
         if (seen) continue;
-        done.push_back(s.n_nu);
-        // this instance's own ladder inputs, in the workspace
-        const Layout &L = P.lay[i];
-        const size_t b = P.base[i];
-        double *gr = at<double>(ws, b + L.gr);
-        double *gd = at<double>(ws, b + L.gd);
-        double *chi = at<double>(ws, b + L.chi);
-        rc = stage_gamma_prep(inst[i], s, ws, b, L, st);
-        if (rc == DF_OK) rc = stage_dual_gf(inst[i], s, inst[i].sigma, gd, gr, st);
-        if (rc == DF_OK) rc = stage_bubble(inst[i], s, gr, chi, st);
+        done.push_back(n_nu);
+        std::vector<LadderInst> table;
+        int items = 0;
+        for (int i = i0; i < n_inst && rc == DF_OK; ++i) {
+            const Shape &s = P.shape[i];
+            if (s.n_nu != n_nu) continue;
+            const Layout &L = P.lay[i];
+            const size_t b = P.base[i];
+            double *gr = at<double>(ws, b + L.gr);
+            double *gd = at<double>(ws, b + L.gd);
+            double *chi = at<double>(ws, b + L.chi);
+            rc = stage_gamma_prep(inst[i], s, ws, b, L, st);
+            if (rc == DF_OK) rc = stage_dual_gf(inst[i], s, inst[i].sigma, gd, gr, st);
+            if (rc == DF_OK) rc = stage_bubble(inst[i], s, gr, chi, st);
+            LadderInst d{};
+            d.gdm = at<double>(ws, b + L.gdm);
+            d.pdm = at<double>(ws, b + L.pdm);
+            d.gtr = at<double>(ws, b + L.gtr);
+            d.gp32 = at<float>(ws, b + L.gp32);
+            d.gtr32 = at<float>(ws, b + L.gtr32);
+            d.chi = chi;
+            d.w = at<double>(ws, b + L.w);
+            d.count = ints + kMaxClasses + i;
+            d.n_nu = s.n_nu;
+            d.n_om = s.n_om;
+            d.N = s.N;
+            d.item0 = items;
+            items += s.items;
+            table.push_back(d);
+        }
         if (rc != DF_OK) break;
+        if (hipMemcpyAsync(at<LadderInst>(ws, P.g.table), table.data(),
+                           table.size() * sizeof(LadderInst), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = DF_E_HIP;
+            break;
+        }
         LadderArgs a{};
-        a.gdm = at<double>(ws, b + L.gdm);
-        a.pdm = at<double>(ws, b + L.pdm);
-        a.gtr = at<double>(ws, b + L.gtr);
-        a.gp32 = at<float>(ws, b + L.gp32);
-        a.gtr32 = at<float>(ws, b + L.gtr32);
-        a.chi = chi;
-        a.w = at<double>(ws, b + L.w);
-        a.fallback_count = ints + kMaxClasses + i;
-        a.n_nu = s.n_nu;
-        a.n_om = s.n_om;
-        a.N = s.N;
+        a.insts = at<LadderInst>(ws, P.g.table);
+        a.n_insts = (int)table.size();
+        a.n_nu = n_nu;
         a.item0 = 0;
-        a.n_items = s.items;
+        a.n_items = items;
         for (int prec : precs) {
         // two rounds over the candidates, each variant keeping its faster
         // round: a variant timed right after the slow pivoting kernels (or
@@ -1080,7 +1102,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         for (int v = 0; v < LV_COUNT; ++v) vms[v] = -1.f;
         for (int round = 0; round < 2 && rc == DF_OK; ++round)
         for (int v = 0; v < LV_COUNT && rc == DF_OK; ++v) {
-            if (!variant_supports(v, s.n_nu, prec)) continue;
+            if (!variant_supports(v, n_nu, prec)) continue;
             constexpr int kReps = 3;
             float ms = 0.f;
             for (int r = 0; r <= kReps && rc == DF_OK; ++r) {   // r = 0: untimed first launch
@@ -1098,7 +1120,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         int best = -1;
         for (int v = 0; v < LV_COUNT; ++v)
             if (vms[v] >= 0.f && (best < 0 || vms[v] < vms[best])) best = v;
-        if (rc == DF_OK && best >= 0) set_tuned_variant(prec, s.n_nu, best);
+        if (rc == DF_OK && best >= 0) set_tuned_variant(prec, n_nu, best);
         }
     }
     (void)hipEventDestroy(e0);
