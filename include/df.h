@@ -167,7 +167,11 @@ int df_bubble(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
 /* eqs. (spin_symm), (dual_ladder), (lin_alg_inv) and the radius test; Gamma^(2) of
  * eq. (sd).  Reads gamma_uu, gamma_ud, chi.  Writes w and, when non-NULL, logdet
  * and status.  opts may be NULL (DF_FP64); DF_ADAPTIVE is rejected here
- * (DF_E_INVAL).  Returns DF_OK; the per-ladder outcome is in status. */
+ * (DF_E_INVAL).  Returns DF_OK; the per-ladder outcome is in status.  Several
+ * instances on a stream that is not being captured run as df_iterate runs them,
+ * one fused launch per kernel class over a device table of the instances (the
+ * table upload synchronises the stream once); under capture, one launch per
+ * instance. */
 int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
                     void *ws, size_t ws_bytes, df_stream_t stream);
 

@@ -734,7 +734,43 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
     if (rc != DF_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int prec = opts ? opts->prec : DF_FP64;
+    const bool sym = opts && opts->symmetry;
     int *ints = at<int>(ws, P.g.ints);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess) return DF_E_HIP;
+    if (n_inst > 1 && cap == hipStreamCaptureStatusNone) {
+        // several instances, not captured: the fused launches of df_iterate (one
+        // per kernel class over a device table of the instances)
+        std::vector<int> act(n_inst), pr(n_inst, prec);
+        for (int i = 0; i < n_inst; ++i) {
+            act[i] = i;
+            rc = stage_gamma_prep(inst[i], P.shape[i], ws, P.base[i], P.lay[i], st);
+            if (rc == DF_OK && sym) rc = stage_sym_tables(P.shape[i], ws, P.base[i], P.lay[i], st);
+            if (rc != DF_OK) return rc;
+        }
+        Fused F;
+        rc = build_fused(inst, P, act, pr, sym, ws, &F, st);
+        if (rc != DF_OK) return rc;
+        HIPCHK(launch_zero_ints(ints, kMaxClasses + n_inst, st));
+        for (size_t c = 0; c < F.cls.size(); ++c) {
+            const FusedClass &k = F.cls[c];
+            LadderArgs a{};
+            a.insts = at<LadderInst>(ws, P.g.table) + k.t0;
+            a.n_insts = k.t1 - k.t0;
+            a.n_nu = k.n_nu;
+            a.item0 = 0;
+            a.n_items = k.items;
+            rc = launch_ladder_variant(k.variant, a, at<int>(ws, P.g.queue) + k.queue_off, ints + c, st);
+            if (rc != DF_OK) return rc;
+        }
+        if (sym)
+            for (int i = 0; i < n_inst; ++i) {
+                rc = stage_sym_expand(P.shape[i], ws, P.base[i], P.lay[i], inst[i].w, inst[i].logdet,
+                                      inst[i].status, st);
+                if (rc != DF_OK) return rc;
+            }
+        return DF_OK;
+    }
     // one launch per instance with plain kernel arguments (capturable)
     for (int i = 0; i < n_inst; ++i) {
         const Shape &s = P.shape[i];
@@ -759,7 +795,6 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         a.N = s.N;
         a.item0 = 0;
         a.n_items = s.items;
-        const bool sym = opts && opts->symmetry;
         if (sym) {
             rc = stage_sym_tables(s, ws, b, L, st);
             if (rc != DF_OK) return rc;
