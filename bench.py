@@ -36,13 +36,14 @@ ACCEL = 5                    # Anderson history depth of the accelerated paths
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(kernel: str, workgroups: int):
-    """HBM bytes per launch from the committed PMC summary, if it still matches.
+def measured_traffic(kernel: str, workgroups: int, per: int = 1):
+    """HBM bytes per instance from the committed PMC summary, if it still matches.
 
     profiles/ladder_traffic.json records calibrated FETCH_SIZE + WRITE_SIZE of
-    the ladder kernels (one instance per launch) together with a hash of
-    their sources; when the sources have changed since, the figures no longer
-    apply and None is returned.
+    the ladder kernels per dispatch of `workgroups` work-groups, together with
+    a hash of their sources; the figure is divided by the `per` instances such
+    a dispatch covers.  When the sources have changed since, the figures no
+    longer apply and None is returned.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", "ladder_traffic.json")
@@ -58,7 +59,7 @@ def measured_traffic(kernel: str, workgroups: int):
                 h.update(f.read())
         if h.hexdigest()[:16] != rec["source_sha256_16"]:
             return None
-        return float(entry["traffic_bytes"])
+        return float(entry["traffic_bytes"]) / per
     except (OSError, KeyError, ValueError):
         return None
 
@@ -142,7 +143,9 @@ def orbit_count(D, nk):
 
 
 def ladder_launch_ms(B, insts, ws, prec, stream, reps, symmetry=0):
-    """Average duration of one ladder launch (one instance), HIP events on the launch stream."""
+    """Ladder time per instance: df_ladder_solve over all instances (one fused launch
+    per kernel class, as in the loop), HIP events on the launch stream, divided by
+    the instance count."""
     import numpy as np
     import torch
     ms = []
@@ -191,7 +194,9 @@ KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}>", "gjb_o3": "k_ladder_gjb_f64_o3
                  "fp32_o5": "k_ladder_fp32_o5<{np}>"}
 
 
-def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
+def roofline_of(prec, B, n_om, N, n_nu, lad_ms, n_inst=1):
+    """Roofline of the ladder kernel per instance; lad_ms is the time per instance
+    (launches fused over n_inst instances, as the loop runs them)."""
     flops_launch = 2 * n_om * N * ladder_flops(n_nu)
     variant = B.df_ladder_variant(n_nu, prec)
     kernel_name = KERNEL_SYMBOL[variant].format(np=n_nu)
@@ -208,7 +213,8 @@ def roofline_of(prec, B, n_om, N, n_nu, lad_ms):
         peak = 3.0 / t_unit
     achieved = flops_launch / (lad_ms * 1e-3) / 1e12
     return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": measured_traffic(kernel_name, 2 * n_om * N),
+            "frac": achieved / peak,
+            "traffic": measured_traffic(kernel_name, 2 * n_om * N * n_inst, n_inst),
             "kernel": kernel_name, "variant": variant, "launch_ms": lad_ms,
             "algorithmic_flops_per_launch": flops_launch}
 
@@ -327,7 +333,7 @@ def main():
     p0 = problems[0]
     reps = max(3, args.steps)
     lad_ms = ladder_launch_ms(B, insts, ws, prec, stream, reps)
-    roof = roofline_of(prec, B, p0.n_om, p0.N, p0.n_nu, lad_ms)
+    roof = roofline_of(prec, B, p0.n_om, p0.N, p0.n_nu, lad_ms, len(insts))
 
     if args.copy_calibration:
         # a plain copy kernel of known size: 256 MiB read + 256 MiB written
@@ -349,7 +355,8 @@ def main():
                 ms = lad_ms if pr == prec else ladder_launch_ms(B, insts, ws, pr, stream, reps)
                 entry = {"ladder_variant": B.df_ladder_variant(p0.n_nu, pr), "ladder_launch_ms": ms,
                          "ladder_solves_per_s": 2 * p0.n_om * p0.N / (ms * 1e-3),
-                         "roofline_frac": roofline_of(pr, B, p0.n_om, p0.N, p0.n_nu, ms)["frac"]}
+                         "roofline_frac": roofline_of(pr, B, p0.n_om, p0.N, p0.n_nu, ms,
+                                                     len(insts))["frac"]}
             if pr != B.DF_FP32:       # FP32 alone does not reach the FP64 fixed point
                 conv = converge_each(B, problems, insts, ws, pr, stream, args.graph)
                 entry.update({"s_per_converged_sigma": float(np.mean([c["seconds"] for c in conv])),
