@@ -8,7 +8,7 @@
 //      partial-pivoting kernel;
 //   2. X ~ D^-1 by the certified blocked Gauss-Jordan sweep in FP32;
 //   3. Z0 = X gamma                               (FP32 MFMA)
-//      E  = gamma - D Z0 = gamma - Z0 + gamma (chi Z0)   (FP64 MFMA, exact Z0)
+//      E  = gamma - D Z0 = gamma - Z0 + (gamma diag chi) Z0   (FP64 MFMA, exact Z0)
 //      Gamma_nn = (Z0)_nn + (X E)_nn              (FP64 accumulation)
 //   This is one step of iterative refinement of the solve D Z = gamma,
 //   restricted to the diagonal that the Schwinger-Dyson step needs.  The
@@ -318,7 +318,7 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
             }
         }
 
-        // ---- E += gamma (chi Z0) on the FP64 matrix cores, k = 4 s + lg.  The
+        // ---- E += (gamma diag chi) Z0 on the FP64 matrix cores, k = 4 s + lg.  The
         // operands of step s + 1 are requested once those of step s have
         // arrived, so their latency hides behind step s's products (scheduling
         // barriers keep the compiler from sinking the requests to their use).
@@ -345,16 +345,18 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
                     x_nx = ld(chi, (size_t)min(kn, nm1) * N + q);
                 }
                 __builtin_amdgcn_sched_barrier(0);   // the requests stay ahead of the products
-                // no mask on gamma: rows k >= n_nu of Z0 are exactly zero (X is the
-                // identity there and gamma was masked in Z0), and rows ia >= n_nu of
-                // E only ever meet the exact zeros of X off its n_nu x n_nu block
-                const cd ga = g0;
+                // A operand M_ik = gamma_ik chi_k (FP64), B operand Z0_kj: one complex
+                // product per k instead of one per tile.  No mask: rows k >= n_nu of
+                // Z0 are exactly zero (X is the identity there and gamma was masked
+                // in Z0), and rows ia >= n_nu of E only ever meet the exact zeros of
+                // X off its n_nu x n_nu block
+                const cd ga = g0 * xk;
                 cf z[NT];
 #pragma unroll
                 for (int tc = 0; tc < NT; ++tc) z[tc] = sh.Zs[k][zs_col<NP>(k, 16 * tc + lj)];
 #pragma unroll
                 for (int tc = 0; tc < NT; ++tc) {
-                    const cd b = xk * cd{(double)z[tc].re, (double)z[tc].im};
+                    const cd b = {(double)z[tc].re, (double)z[tc].im};
                     Er[tc] = MT<double>::mma(ga.re, b.re, Er[tc]);
                     Er[tc] = MT<double>::mma_na(ga.im, b.im, Er[tc]);
                     Ei[tc] = MT<double>::mma(ga.re, b.im, Ei[tc]);
