@@ -245,6 +245,41 @@ def lattice_leg(B, problems, insts, stream, log):
     return out
 
 
+def batched_leg(B, log):
+    """The uneven batched workload (64 seeded instances, D in {2, 3}, 2D 16^2..64^2,
+    3D 8^3..16^3, n_nu in {32, 64, 128}) in fused, graph-captured iterations:
+    time per outer iteration of all 64 and the ladder solves per second, FP64,
+    after autotuning each n_nu class on its fused launch."""
+    import numpy as np
+    import torch
+    from paper_1507_00895_amd import inputs as I
+    probs = I.batched_problems(I.draw_batched_params())
+    insts = [B.make_instance(p) for p in probs]
+    ws = B.workspace(insts)
+    s = torch.cuda.Stream()
+    B.df_autotune(insts, ws, B.make_opts(prec=B.DF_FP64), stream=s.cuda_stream)
+    opts = B.make_opts(mix=0.5, tol=0.0, max_iter=1, use_graph=1)
+    B.df_iterate(insts, ws, opts, stream=s.cuda_stream, allow=(B.DF_OK, B.DF_W_FALLBACK))
+    s.synchronize()
+    steps = 3
+    opts = B.make_opts(mix=0.5, tol=0.0, max_iter=steps, use_graph=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.df_iterate(insts, ws, opts, stream=s.cuda_stream, allow=(B.DF_OK, B.DF_W_FALLBACK))
+    s.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    solves = sum(2 * p.n_om * p.N for p in probs)
+    out = {"instances": len(probs), "ms_per_iteration": dt * 1e3,
+           "ladder_solves_per_iteration": solves, "solves_per_s": solves / dt,
+           "ladder_classes": sorted({p.n_nu for p in probs}),
+           "variants": {n: B.df_ladder_variant(n, B.DF_FP64) for n in sorted({p.n_nu for p in probs})}}
+    log(f"batched uneven workload: {out['ms_per_iteration']:.1f} ms per iteration of "
+        f"{len(probs)} instances, {out['solves_per_s'] / 1e6:.1f} M solves/s")
+    del insts, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def warm_start_leg(problems, args, log):
     """Train the warm-start network on the method's own converged Sigma~ at
     this workload's shape, then predict the three instances' Sigma~."""
@@ -399,6 +434,7 @@ def main():
                 log(f"{name}: {sec:.3f} s per converged Sigma~")
             paths["warm_network"] = info
         paths["lattice_observables"] = lattice_leg(B, problems, insts, stream, log)
+        paths["batched_uneven"] = batched_leg(B, log)
 
     out = {
         "metric": "ladder (q,omega) solves/s + s per converged Sigma~: FP64 vs FP32-MFMA+refine at 1e-9 rel",
