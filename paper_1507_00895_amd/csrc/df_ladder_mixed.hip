@@ -10,6 +10,7 @@
 //   3. Z0 = X gamma                               (FP32 MFMA)
 //      E  = gamma - D Z0 = gamma - Z0 + (gamma diag chi) Z0   (FP64 MFMA, exact Z0)
 //      Gamma_nn = (Z0)_nn + (X E)_nn              (FP64 accumulation)
+//   Both matrix products take three real products per complex one.
 //   This is one step of iterative refinement of the solve D Z = gamma,
 //   restricted to the diagonal that the Schwinger-Dyson step needs.  The
 //   remaining error is of order (kappa eps32)^2 relative, with kappa the
@@ -238,11 +239,14 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
         const float *gp = a.gp32 + 4 * (size_t)cm * nn;   // (gamma, gamma_ij gamma_ji) in FP32
         // ---- Z0 = X gamma on the FP32 matrix cores; the wave's X tiles reach the
         // operand layout through its own LDS slot
-        f4 Zr[NT], Zi[NT];
+        // three real products per complex one: P1 = X_re g_re, P2 = X_im g_im,
+        // P3 = (X_re + X_im)(g_re + g_im); Z0 = (P1 - P2, P3 - P1 - P2)
+        f4 P1[NT], P2[NT], P3[NT];
 #pragma unroll
         for (int tc = 0; tc < NT; ++tc) {
-            Zr[tc] = f4{0, 0, 0, 0};
-            Zi[tc] = f4{0, 0, 0, 0};
+            P1[tc] = f4{0, 0, 0, 0};
+            P2[tc] = f4{0, 0, 0, 0};
+            P3[tc] = f4{0, 0, 0, 0};
         }
         // gamma goes through LDS one 16-row block at a time, loaded once for
         // the four waves (FP32 pairs of the vertex copy, padding zeroed); the
@@ -276,13 +280,13 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
 #pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
                 const cf xa = sh.z0.Tw[w][lj][4 * k4 + lg];
+                const float xs = xa.re + xa.im;
 #pragma unroll
                 for (int tc = 0; tc < NT; ++tc) {
                     const cf b = sh.z0.Gs[kt & 1][4 * k4 + lg][16 * tc + lj];
-                    Zr[tc] = MT<float>::mma(xa.re, b.re, Zr[tc]);
-                    Zr[tc] = MT<float>::mma_na(xa.im, b.im, Zr[tc]);
-                    Zi[tc] = MT<float>::mma(xa.re, b.im, Zi[tc]);
-                    Zi[tc] = MT<float>::mma(xa.im, b.re, Zi[tc]);
+                    P1[tc] = MT<float>::mma(xa.re, b.re, P1[tc]);
+                    P2[tc] = MT<float>::mma(xa.im, b.im, P2[tc]);
+                    P3[tc] = MT<float>::mma(xs, b.re + b.im, P3[tc]);
                 }
             }
             if (kt + 1 < NT) store_block(kt + 1);
@@ -295,37 +299,59 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 16 * w + MT<float>::row(lg, r);
-                sh.Zs[i][zs_col<NP>(i, 16 * tc + lj)] = cf{Zr[tc][r], Zi[tc][r]};
+                sh.Zs[i][zs_col<NP>(i, 16 * tc + lj)] =
+                    cf{P1[tc][r] - P2[tc][r], P3[tc][r] - P1[tc][r] - P2[tc][r]};
             }
         __syncthreads();
-        // ---- E = gamma - Z0 on the wave's rows
-        d4 Er[NT], Ei[NT];
+        // the diagonal of Z0 on this wave's rows, before E replaces Z0
+        cd zd[4];
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) {
-            int j = 16 * tc + lj;
-            asm volatile("" : "+v"(j));
-            cd gv[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                gv[r] = ld(gam, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * w + MT<float>::row(lg, r);
-                const bool in = (i < n_nu) && (j < n_nu);
-                const cf z = sh.Zs[i][zs_col<NP>(i, j)];
-                Er[tc][r] = (in ? gv[r].re : 0.0) - (double)z.re;
-                Ei[tc][r] = (in ? gv[r].im : 0.0) - (double)z.im;
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int n = 16 * w + MT<float>::row(lg, r);
+            const cf z = sh.Zs[n][zs_col<NP>(n, n)];
+            zd[r] = {(double)z.re, (double)z.im};
         }
 
-        // ---- E += (gamma diag chi) Z0 on the FP64 matrix cores, k = 4 s + lg.  The
-        // operands of step s + 1 are requested once those of step s have
-        // arrived, so their latency hides behind step s's products (scheduling
-        // barriers keep the compiler from sinking the requests to their use).
-        {
-            const int lp = 4 * (lj & 3) + (lj >> 2);   // perm(lj)
-            const int ia = 16 * w + lp;
-            const size_t rowa = (size_t)min(ia, nm1) * n_nu;
+        // ---- E = gamma - Z0 + (gamma diag chi) Z0 on the FP64 matrix cores, on
+        // the wave's rows, in passes of two tile columns.  Three real products
+        // per complex one, with the start value folded in: A1 = E0_re + sum
+        // M_re Z_re, A2 = sum M_im Z_im, A3 = E0_re + E0_im + sum (M_re + M_im)
+        // (Z_re + Z_im) give E = (A1 - A2, A3 - A1 - A2).  A pass's E goes to
+        // LDS, in FP32, over the Z0 columns that no wave reads after it: E is
+        // of order kappa eps32 |gamma|, so its own FP32 rounding adds about
+        // 6e-8 of that to Gamma.
+        constexpr int PW = 2;
+        const int lp = 4 * (lj & 3) + (lj >> 2);   // perm(lj)
+        const int ia = 16 * w + lp;
+        const size_t rowa = (size_t)min(ia, nm1) * n_nu;
+#pragma unroll
+        for (int p0 = 0; p0 < NT; p0 += PW) {
+            d4 A1[PW], A2[PW], A3[PW];
+#pragma unroll
+            for (int u = 0; u < PW; ++u) {
+                if (p0 + u >= NT) continue;
+                int j = 16 * (p0 + u) + lj;
+                asm volatile("" : "+v"(j));
+                cd gv[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    gv[r] = ld(gam, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * w + MT<float>::row(lg, r);
+                    const bool in = (i < n_nu) && (j < n_nu);
+                    const cf z = sh.Zs[i][zs_col<NP>(i, j)];
+                    const double er = (in ? gv[r].re : 0.0) - (double)z.re;
+                    const double ei = (in ? gv[r].im : 0.0) - (double)z.im;
+                    A1[u][r] = er;
+                    A2[u][r] = 0.0;
+                    A3[u][r] = er + ei;
+                }
+            }
+            // k = 4 s + lg.  The operands of step s + 1 are requested once those
+            // of step s have arrived, so their latency hides behind step s's
+            // products (scheduling barriers keep the compiler from sinking the
+            // requests to their use).
             cd g_nx, x_nx;
             {
                 int k = lg;
@@ -345,43 +371,38 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
                     x_nx = ld(chi, (size_t)min(kn, nm1) * N + q);
                 }
                 __builtin_amdgcn_sched_barrier(0);   // the requests stay ahead of the products
-                // A operand M_ik = gamma_ik chi_k (FP64), B operand Z0_kj: one complex
-                // product per k instead of one per tile.  No mask: rows k >= n_nu of
-                // Z0 are exactly zero (X is the identity there and gamma was masked
-                // in Z0), and rows ia >= n_nu of E only ever meet the exact zeros of
-                // X off its n_nu x n_nu block
+                // A operand M_ik = gamma_ik chi_k (FP64), B operand Z0_kj.  No mask:
+                // rows k >= n_nu of Z0 are exactly zero (X is the identity there
+                // and gamma was masked in Z0), and rows ia >= n_nu of E only ever
+                // meet the exact zeros of X off its n_nu x n_nu block
                 const cd ga = g0 * xk;
-                cf z[NT];
+                const double gs = ga.re + ga.im;
+                cf z[PW];
 #pragma unroll
-                for (int tc = 0; tc < NT; ++tc) z[tc] = sh.Zs[k][zs_col<NP>(k, 16 * tc + lj)];
+                for (int u = 0; u < PW; ++u)
+                    if (p0 + u < NT) z[u] = sh.Zs[k][zs_col<NP>(k, 16 * (p0 + u) + lj)];
 #pragma unroll
-                for (int tc = 0; tc < NT; ++tc) {
-                    const cd b = {(double)z[tc].re, (double)z[tc].im};
-                    Er[tc] = MT<double>::mma(ga.re, b.re, Er[tc]);
-                    Er[tc] = MT<double>::mma_na(ga.im, b.im, Er[tc]);
-                    Ei[tc] = MT<double>::mma(ga.re, b.im, Ei[tc]);
-                    Ei[tc] = MT<double>::mma(ga.im, b.re, Ei[tc]);
+                for (int u = 0; u < PW; ++u) {
+                    if (p0 + u >= NT) continue;
+                    const double br = (double)z[u].re, bi = (double)z[u].im;
+                    A1[u] = MT<double>::mma(ga.re, br, A1[u]);
+                    A2[u] = MT<double>::mma(ga.im, bi, A2[u]);
+                    A3[u] = MT<double>::mma(gs, br + bi, A3[u]);
+                }
+            }
+            __syncthreads();   // every wave is done with these columns of Z0
+#pragma unroll
+            for (int u = 0; u < PW; ++u) {
+                if (p0 + u >= NT) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * w + MT<float>::row(lg, r);
+                    const double er = A1[u][r] - A2[u][r];
+                    const double ei = A3[u][r] - A1[u][r] - A2[u][r];
+                    sh.Zs[i][zs_col<NP>(i, 16 * (p0 + u) + lj)] = cf{(float)er, (float)ei};
                 }
             }
         }
-        // the diagonal of Z0 on this wave's rows, before E replaces Z0
-        cd zd[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int n = 16 * w + MT<float>::row(lg, r);
-            const cf z = sh.Zs[n][zs_col<NP>(n, n)];
-            zd[r] = {(double)z.re, (double)z.im};
-        }
-        __syncthreads();
-        // ---- E to LDS in FP32: E is of order kappa eps32 |gamma|, so its own
-        // FP32 rounding adds about 6e-8 of that to Gamma
-#pragma unroll
-        for (int tc = 0; tc < NT; ++tc)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * w + MT<float>::row(lg, r);
-                sh.Zs[i][zs_col<NP>(i, 16 * tc + lj)] = cf{(float)Er[tc][r], (float)Ei[tc][r]};
-            }
         __syncthreads();
         // ---- (X E)_nn for the wave's rows n: lane lj takes k = 16 tc + lj
         cd acc[4];
