@@ -84,7 +84,10 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
         return;   // uniform: every thread of the work-group leaves here
     }
 
-    gj_sweep<double, NP>(Cr, Ci, sh);
+    // look-ahead inversion at NP = 96, where it removes the spills (7.14 -> 6.76
+    // ms per instance); at 64 it costs the four-wave build registers (3.20 ->
+    // 4.20 ms), at 128 it measured even (12.94 -> 13.08 ms)
+    gj_sweep<double, NP, (NP == 96)>(Cr, Ci, sh);
 
     if (w == 0) {
         cd ldv;

@@ -164,7 +164,7 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
         return;   // uniform: every thread of the work-group leaves here
     }
 
-    gj_sweep<float, NP>(Cr, Ci, sh.gj);
+    gj_sweep<float, NP, true>(Cr, Ci, sh.gj);   // look-ahead inversion
 
     if (w == 0) {
         cd ldv;
