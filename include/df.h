@@ -210,7 +210,11 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
 /* Name of the ladder kernel variant that calls for this n_nu and precision use
  * now ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4", "mixed_o4"),
  * for prec DF_FP64, DF_FP32_REFINE or DF_FP32, written to the
- * host buffer name (NUL-terminated, name_len bytes at most). */
+ * host buffer name (NUL-terminated, name_len bytes at most).  Sizes: the
+ * FP64 variants serve n_nu <= 128 ("gjb_o3" / "gjb_o4" up to 64); the refined
+ * variants ("mixed*") n_nu <= 64; "fp32" n_nu <= 128, "fp32_o4" / "fp32_o5"
+ * up to 64.  A precision class without a kernel for n_nu is served by the
+ * FP64 variants. */
 int df_ladder_variant(int32_t n_nu, int32_t prec, char *name, size_t name_len);
 
 /* Record a choice by hand, as df_autotune would: later calls for this n_nu and

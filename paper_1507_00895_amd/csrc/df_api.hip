@@ -224,6 +224,7 @@ int env_variant() {
 int default_variant(int n_nu, int prec) {
     if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(n_nu) != 0) return LV_MIXED_O3;
     if (prec == DF_FP32 && ladder_mixed_padded_size(n_nu) != 0) return LV_FP32_O4;
+    if (prec == DF_FP32 && ladder_fp32_padded_size(n_nu) != 0) return LV_FP32;
     if (ladder_gjb_has_occ3(n_nu)) return LV_GJB_O3;
     if (ladder_gjb_padded_size(n_nu) != 0) return LV_GJB;
     return LV_VECTOR;

@@ -254,6 +254,7 @@ bool ladder_gjb_has_occ3(int n_nu);
 hipError_t launch_ladder_gjb_f64(const LadderArgs &a, int occ, hipStream_t s);
 // mixed precision: FP32 certified sweep + one FP64 residual correction (n_nu <= 64)
 int ladder_mixed_padded_size(int n_nu);
+int ladder_fp32_padded_size(int n_nu);
 bool ladder_mixed_has_occ3(int n_nu);
 hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, hipStream_t s);
 // FP32 only, no refinement (same sizes as the mixed kernel); occ = 4 or 5

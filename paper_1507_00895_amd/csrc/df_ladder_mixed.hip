@@ -505,6 +505,17 @@ int ladder_mixed_padded_size(int n_nu) {
     return 0;   // larger sizes take the FP64 kernels
 }
 
+// The FP32 ladder alone also runs at n_nu = 96 and 128 (six and eight waves,
+// 29 / 38 KB of LDS, the compiler's register budget); the refined kernel
+// stops at 64, where its Z0 / E buffer (NP^2 complex floats) still fits.
+int ladder_fp32_padded_size(int n_nu) {
+    const int p = ladder_mixed_padded_size(n_nu);
+    if (p != 0) return p;
+    if (n_nu <= 96) return 96;
+    if (n_nu <= 128) return 128;
+    return 0;
+}
+
 // three and four work-groups per CU fit the LDS at every size (34 KB at NP = 64)
 bool ladder_mixed_has_occ3(int n_nu) {
     return ladder_mixed_padded_size(n_nu) != 0;
@@ -526,11 +537,19 @@ hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, hipStream_t s) {
 namespace df {
 
 hipError_t launch_ladder_fp32(const LadderArgs &a, int occ, hipStream_t s) {
-    switch (ladder_mixed_padded_size(a.n_nu)) {
+    switch (ladder_fp32_padded_size(a.n_nu)) {
         case 16: return launch_fp32<16>(a, occ, s);
         case 32: return launch_fp32<32>(a, occ, s);
         case 48: return launch_fp32<48>(a, occ, s);
         case 64: return launch_fp32<64>(a, occ, s);
+        case 96:
+            if (occ != 0) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_ladder_fp32<96>), dim3(a.n_items), dim3(96 * 4), 0, s, a);
+            return hipGetLastError();
+        case 128:
+            if (occ != 0) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_ladder_fp32<128>), dim3(a.n_items), dim3(128 * 4), 0, s, a);
+            return hipGetLastError();
         default: return hipErrorInvalidValue;
     }
 }

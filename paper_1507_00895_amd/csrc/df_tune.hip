@@ -66,7 +66,7 @@ int variant_padded_size(int v, int n_nu) {
         case LV_MIXED: return ladder_mixed_padded_size(n_nu);
         case LV_MIXED_O3:
         case LV_MIXED_O4: return ladder_mixed_has_occ3(n_nu) ? ladder_mixed_padded_size(n_nu) : 0;
-        case LV_FP32:
+        case LV_FP32: return ladder_fp32_padded_size(n_nu);
         case LV_FP32_O4:
         case LV_FP32_O5: return ladder_mixed_padded_size(n_nu);
         default: return 0;
@@ -86,13 +86,14 @@ int variant_prec(int v) {
 }
 
 // A request is served by the variants of its own precision class; where that
-// class has no kernel for n_nu (the FP32 kernels stop at n_nu = 64), by the
-// FP64 variants.
+// class has no kernel for n_nu (the refined kernels stop at n_nu = 64, the
+// FP32 ones at 128), by the FP64 variants.
 bool variant_supports(int v, int n_nu, int prec) {
     if (variant_padded_size(v, n_nu) == 0) return false;
     const int vp = variant_prec(v);
     if (vp == prec) return true;
-    return vp == DF_FP64 && prec != DF_FP64 && ladder_mixed_padded_size(n_nu) == 0;
+    const int own = prec == DF_FP32 ? ladder_fp32_padded_size(n_nu) : ladder_mixed_padded_size(n_nu);
+    return vp == DF_FP64 && prec != DF_FP64 && own == 0;
 }
 
 int tuned_variant(int prec, int n_nu) {

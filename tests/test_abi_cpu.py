@@ -166,7 +166,8 @@ def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     assert B.df_ladder_variant(96, B.DF_FP32_REFINE) == "gjb"      # beyond the mixed kernel
     assert B.df_ladder_variant(128, B.DF_FP64) == "gjb"
     assert B.df_ladder_variant(64, B.DF_FP32) == "fp32_o4"
-    assert B.df_ladder_variant(128, B.DF_FP32) == "gjb"
+    assert B.df_ladder_variant(128, B.DF_FP32) == "fp32"            # FP32 alone up to 128
+    assert B.df_ladder_variant(96, B.DF_FP32) == "fp32"
     with pytest.raises(B.DfError):
         B.df_ladder_variant(64, B.DF_ADAPTIVE)
     B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o4")
@@ -175,7 +176,8 @@ def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     for bad in [(96, B.DF_FP64, "gjb_o3"), (128, B.DF_FP64, "gjb_o4"), (64, B.DF_FP64, "mixed"),
                 (64, B.DF_FP32_REFINE, "vector"), (64, B.DF_FP32_REFINE, "fp32_o4"),
                 (96, B.DF_FP32_REFINE, "mixed_o4"), (64, B.DF_FP64, "mixed_o3"),
-                (64, B.DF_FP32, "mixed"), (64, B.DF_FP64, "fp32_o4"), (96, B.DF_FP32, "fp32")]:
+                (64, B.DF_FP32, "mixed"), (64, B.DF_FP64, "fp32_o4"), (96, B.DF_FP32, "fp32_o4"),
+                (128, B.DF_FP32, "fp32_o5"), (128, B.DF_FP32, "gjb")]:
         with pytest.raises(B.DfError) as e:
             B.df_ladder_set_variant(*bad)
         assert e.value.code == B.DF_E_UNSUPPORTED
