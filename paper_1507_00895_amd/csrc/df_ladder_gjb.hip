@@ -41,26 +41,50 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
     const double *pm = a.pdm + 2 * (size_t)cm * nn;
     const double *gtr = a.gtr + 2 * (size_t)cm * nn;
 
-    // ---- D = 1 - gamma diag(chi) in accumulator tiles, t_i = (gamma chi gamma)_ii.
-    // Per tile column, all loads first and without branches (indices clamped
-    // into the matrix, the padding masked afterwards), so that they are in
-    // flight together.
-    d4 Cr[NT], Ci[NT];
-    cd tp[4];
+    // ---- t_i = (gamma chi gamma)_ii = sum_j (gamma_ij gamma_ji) chi_j, on its own
+    // before the D tiles exist, so its loads do not sit beside them.  Per tile
+    // column all loads first and without branches (indices clamped into the
+    // matrix, the padding masked afterwards), so that they are in flight together.
     const int nm1 = n_nu - 1;
+    {
+        cd tp[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
+        for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
+#pragma unroll
+        for (int tc = 0; tc < NT; ++tc) {
+            const int j = 16 * tc + lj;
+            const cd xj = ld(a.chi, ((size_t)im * n_nu + min(j, nm1)) * N + q);
+            cd pv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                pv[r] = ld(pm, (size_t)min(16 * w + MT<double>::row(lg, r), nm1) * n_nu + min(j, nm1));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * w + MT<double>::row(lg, r);
+                const bool in = (i < n_nu) && (j < n_nu);
+                tp[r] = fma_c(tp[r], in ? pv[r] : cd{0.0, 0.0}, xj);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tp[r] = row16_sum(tp[r]);
+        if (lj == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tv[16 * w + MT<double>::row(lg, r)] = tp[r];
+        }
+    }
+
+    // ---- D = 1 - gamma diag(chi) in accumulator tiles (opaque column index:
+    // the chi loads are not shared with the loop above)
+    d4 Cr[NT], Ci[NT];
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) {
-        const int j = 16 * tc + lj;
+        int j = 16 * tc + lj;
+        asm volatile("" : "+v"(j));
         const cd xj = ld(a.chi, ((size_t)im * n_nu + min(j, nm1)) * N + q);
-        cd gv[4], pv[4];
+        cd gv[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const size_t e = (size_t)min(16 * w + MT<double>::row(lg, r), nm1) * n_nu + min(j, nm1);
-            gv[r] = ld(gam, e);
-            pv[r] = ld(pm, e);
-        }
+        for (int r = 0; r < 4; ++r)
+            gv[r] = ld(gam, (size_t)min(16 * w + MT<double>::row(lg, r), nm1) * n_nu + min(j, nm1));
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = 16 * w + MT<double>::row(lg, r);
@@ -68,14 +92,7 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
             const cd x = gv[r] * xj;
             Cr[tc][r] = (((i == j) ? 1.0 : 0.0) - (in ? x.re : 0.0));
             Ci[tc][r] = (in ? -x.im : 0.0);
-            tp[r] = fma_c(tp[r], in ? pv[r] : cd{0.0, 0.0}, xj);
         }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) tp[r] = row16_sum(tp[r]);
-    if (lj == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tv[16 * w + MT<double>::row(lg, r)] = tp[r];
     }
 
     const double cw = gj_certify<double, NP>(Cr, Ci, sh, CERT_ITERS, CERT_MAX_F64);

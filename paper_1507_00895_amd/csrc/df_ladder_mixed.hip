@@ -118,36 +118,38 @@ __device__ __forceinline__ void mixed_body(LadderArgs a0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) tp[r] = {(double)tf[r].re, (double)tf[r].im};
     } else {
-    const int nm1 = n_nu - 1;
+    // t first, on its own, so that its loads do not sit beside the D tiles
 #pragma unroll
-    for (int r = 0; r < 4; ++r) tp[r] = {0.0, 0.0};
+    for (int tc = 0; tc < NT; ++tc) {
+        const int j = 16 * tc + lj;
+        const cd xj = ld(chi, (size_t)min(j, nm1) * N + q);
+        cd pv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            pv[r] = ld(pm, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + MT<float>::row(lg, r);
+            const bool in = (i < n_nu) && (j < n_nu);
+            tp[r] = fma_c(tp[r], in ? pv[r] : cd{0.0, 0.0}, xj);
+        }
+    }
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) {
         int j = 16 * tc + lj;
         asm volatile("" : "+v"(j));   // keeps each tile column's loads in place
         const cd xj = ld(chi, (size_t)min(j, nm1) * N + q);
-        // two rows per batch of loads: the FP32 kernels run on a tighter
-        // register budget
+        cd gv[4];
 #pragma unroll
-        for (int r0 = 0; r0 < 4; r0 += 2) {
-            cd gv[2], pv[2];
+        for (int r = 0; r < 4; ++r)
+            gv[r] = ld(gam, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const size_t e =
-                    (size_t)min(16 * w + MT<float>::row(lg, r0 + k), nm1) * n_nu + min(j, nm1);
-                gv[k] = ld(gam, e);
-                pv[k] = ld(pm, e);
-            }
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int r = r0 + k;
-                const int i = 16 * w + MT<float>::row(lg, r);
-                const bool in = (i < n_nu) && (j < n_nu);
-                const cd x = gv[k] * xj;
-                Cr[tc][r] = (float)(((i == j) ? 1.0 : 0.0) - (in ? x.re : 0.0));
-                Ci[tc][r] = (float)(in ? -x.im : 0.0);
-                tp[r] = fma_c(tp[r], in ? pv[k] : cd{0.0, 0.0}, xj);
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + MT<float>::row(lg, r);
+            const bool in = (i < n_nu) && (j < n_nu);
+            const cd x = gv[r] * xj;
+            Cr[tc][r] = (float)(((i == j) ? 1.0 : 0.0) - (in ? x.re : 0.0));
+            Ci[tc][r] = (float)(in ? -x.im : 0.0);
         }
     }
     }
