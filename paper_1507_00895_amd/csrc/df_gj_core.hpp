@@ -403,16 +403,18 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
                     gim[k4] = g.im;
                 }
             } else {
-                v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};
+                // G = -A_wt A_tt^-1 in the 3M form: T1 = a_re b_re, T2 = a_im b_im,
+                // P3 = (a_re + a_im)(b_re + b_im); G = (T2 - T1, T1 + T2 - P3)
+                v4 T1 = {0, 0, 0, 0}, T2 = {0, 0, 0, 0}, P3 = {0, 0, 0, 0};
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     const ct xa = sh.Xw[w][lj][4 * k4 + lg];
                     const ct b = sh.Xw[t][4 * k4 + lg][lj];
-                    Gr = MT<T>::mma_na(xa.re, b.re, Gr);
-                    Gr = MT<T>::mma(xa.im, b.im, Gr);
-                    Gi = MT<T>::mma_na(xa.re, b.im, Gi);
-                    Gi = MT<T>::mma_na(xa.im, b.re, Gi);
+                    T1 = MT<T>::mma(xa.re, b.re, T1);
+                    T2 = MT<T>::mma(xa.im, b.im, T2);
+                    P3 = MT<T>::mma(xa.re + xa.im, b.re + b.im, P3);
                 }
+                const v4 Gr = T2 - T1, Gi = T1 + T2 - P3;
                 Cr[0] = Gr;
                 Ci[0] = Gi;
                 wave_sync_lds();
@@ -449,16 +451,18 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
             // G_w in LDS (this wave's exchange slot): the inverse for w = t (its
             // diagonal minus one below), -A_wt A_tt^-1 formed here for the others
             if (w != t) {
-                v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};
+                // G = -A_wt A_tt^-1 in the 3M form: T1 = a_re b_re, T2 = a_im b_im,
+                // P3 = (a_re + a_im)(b_re + b_im); G = (T2 - T1, T1 + T2 - P3)
+                v4 T1 = {0, 0, 0, 0}, T2 = {0, 0, 0, 0}, P3 = {0, 0, 0, 0};
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     const ct xa = sh.Xw[w][lj][4 * k4 + lg];
                     const ct b = sh.Xw[t][4 * k4 + lg][lj];
-                    Gr = MT<T>::mma_na(xa.re, b.re, Gr);
-                    Gr = MT<T>::mma(xa.im, b.im, Gr);
-                    Gi = MT<T>::mma_na(xa.re, b.im, Gi);
-                    Gi = MT<T>::mma_na(xa.im, b.re, Gi);
+                    T1 = MT<T>::mma(xa.re, b.re, T1);
+                    T2 = MT<T>::mma(xa.im, b.im, T2);
+                    P3 = MT<T>::mma(xa.re + xa.im, b.re + b.im, P3);
                 }
+                const v4 Gr = T2 - T1, Gi = T1 + T2 - P3;
                 Cr[0] = Gr;
                 Ci[0] = Gi;
                 wave_sync_lds();
@@ -542,16 +546,18 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                     gim[k4] = g.im;
                 }
             } else {
-                v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};
+                // G = -A_wt A_tt^-1 in the 3M form: T1 = a_re b_re, T2 = a_im b_im,
+                // P3 = (a_re + a_im)(b_re + b_im); G = (T2 - T1, T1 + T2 - P3)
+                v4 T1 = {0, 0, 0, 0}, T2 = {0, 0, 0, 0}, P3 = {0, 0, 0, 0};
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     const ct xa = sh.Xw[w][lj][4 * k4 + lg];
                     const ct b = sh.Xw[t][4 * k4 + lg][lj];
-                    Gr = MT<T>::mma_na(xa.re, b.re, Gr);
-                    Gr = MT<T>::mma(xa.im, b.im, Gr);
-                    Gi = MT<T>::mma_na(xa.re, b.im, Gi);
-                    Gi = MT<T>::mma_na(xa.im, b.re, Gi);
+                    T1 = MT<T>::mma(xa.re, b.re, T1);
+                    T2 = MT<T>::mma(xa.im, b.im, T2);
+                    P3 = MT<T>::mma(xa.re + xa.im, b.re + b.im, P3);
                 }
+                const v4 Gr = T2 - T1, Gi = T1 + T2 - P3;
                 Cr[0] = Gr;
                 Ci[0] = Gi;
                 wave_sync_lds();
@@ -602,16 +608,18 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
             // G_w in LDS (this wave's exchange slot): the inverse for w = t (its
             // diagonal minus one below), -A_wt A_tt^-1 formed here for the others
             if (w != t) {
-                v4 Gr = {0, 0, 0, 0}, Gi = {0, 0, 0, 0};
+                // G = -A_wt A_tt^-1 in the 3M form: T1 = a_re b_re, T2 = a_im b_im,
+                // P3 = (a_re + a_im)(b_re + b_im); G = (T2 - T1, T1 + T2 - P3)
+                v4 T1 = {0, 0, 0, 0}, T2 = {0, 0, 0, 0}, P3 = {0, 0, 0, 0};
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
                     const ct xa = sh.Xw[w][lj][4 * k4 + lg];
                     const ct b = sh.Xw[t][4 * k4 + lg][lj];
-                    Gr = MT<T>::mma_na(xa.re, b.re, Gr);
-                    Gr = MT<T>::mma(xa.im, b.im, Gr);
-                    Gi = MT<T>::mma_na(xa.re, b.im, Gi);
-                    Gi = MT<T>::mma_na(xa.im, b.re, Gi);
+                    T1 = MT<T>::mma(xa.re, b.re, T1);
+                    T2 = MT<T>::mma(xa.im, b.im, T2);
+                    P3 = MT<T>::mma(xa.re + xa.im, b.re + b.im, P3);
                 }
+                const v4 Gr = T2 - T1, Gi = T1 + T2 - P3;
                 Cr[0] = Gr;
                 Ci[0] = Gi;
                 wave_sync_lds();
