@@ -101,10 +101,10 @@ __device__ __forceinline__ void gjb_body(LadderArgs a0) {
         return;   // uniform: every thread of the work-group leaves here
     }
 
-    // look-ahead inversion at NP = 96, where it removes the spills (7.14 -> 6.76
-    // ms per instance); at 64 it costs the four-wave build registers (3.20 ->
-    // 4.20 ms), at 128 it measured even (12.94 -> 13.08 ms)
-    gj_sweep<double, NP, (NP == 96)>(Cr, Ci, sh);
+    // look-ahead inversion up to NP = 96: at 96 it removes the spills (7.14 ->
+    // 6.76 ms per instance), at 32 / 48 / 64 the fastest builds gain 2 / 3 / 1 %
+    // now that t is formed before the D tiles; at 128 it measured even
+    gj_sweep<double, NP, (NP != 128)>(Cr, Ci, sh);
 
     if (w == 0) {
         cd ldv;
