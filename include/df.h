@@ -195,8 +195,8 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
  * inputs of all instances with that n_nu in the workspace (G~ from sigma,
  * NULL = zero, and chi), times every ladder kernel variant able to run them on
  * one fused launch over those instances - the launch df_iterate makes - (three
- * launches after an untimed one, HIP events on the stream, two rounds over the
- * candidates, each variant keeping its faster round), and keeps the fastest
+ * launches after an untimed one, HIP events on the stream, two passes over the
+ * candidates, each variant keeping its faster pass), and keeps the fastest
  * for later calls of this process.  When the environment
  * variable DF_TUNE_CACHE names a file, choices are read from it on first use
  * and the whole table is written back here.  Every variant gives results of

@@ -1131,12 +1131,12 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         a.item0 = 0;
         a.n_items = items;
         for (int prec : precs) {
-        // two rounds over the candidates, each variant keeping its faster
-        // round: a variant timed right after the slow pivoting kernels (or
-        // while clocks settle) is not judged on that round alone
+        // two passes over the candidates, each variant keeping its faster
+        // pass: a variant timed right after the slow pivoting kernels (or
+        // while clocks settle) is not ranked on that pass alone
         float vms[LV_COUNT];
         for (int v = 0; v < LV_COUNT; ++v) vms[v] = -1.f;
-        for (int round = 0; round < 2 && rc == DF_OK; ++round)
+        for (int pass = 0; pass < 2 && rc == DF_OK; ++pass)
         for (int v = 0; v < LV_COUNT && rc == DF_OK; ++v) {
             if (!variant_supports(v, n_nu, prec)) continue;
             constexpr int kReps = 3;
