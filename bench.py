@@ -127,8 +127,15 @@ def cpu_baseline(problems, budget_s: float = 20.0):
     except Exception:
         cores = os.cpu_count()
     threads = int(os.environ.get("OMP_NUM_THREADS", cores) or cores)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": solves / t_iter, "unit": "solves/s", "cores": min(cores, threads),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "cpu_count": os.cpu_count(),
+            "affinity_cores": cores,
             "sample": (f"one outer iteration of the U={p.U} instance: dual GF, bubble and "
                        f"Schwinger-Dyson in full; ladder on {n_sl} of {p.n_om} bosonic slices "
                        f"({2 * n_sl * p.N} solves, {t_lad:.1f} s), scaled to all slices; "

@@ -92,3 +92,13 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_cpu_baseline_on_a_small_problem():
+    from paper_1507_00895_amd import inputs as I
+    p = I.atomic_limit_problem(2, 8, 16, 3, 10.0, 2.0, 0.1)
+    out = bench.cpu_baseline([p], budget_s=0.5)
+    assert out["kind"] == "oracle" and out["unit"] == "solves/s"
+    assert out["value"] > 0 and out["cores"] >= 1
+    assert out["affinity_cores"] >= 1 and out["cpu_count"] >= 1
+    assert "of 3 bosonic slices" in out["sample"]
