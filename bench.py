@@ -1,7 +1,7 @@
 """Benchmark of the ladder dual-fermion hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|mixed|fp32]
-                    [--no-cpu-baseline] [--no-converge] [--no-warm]
+                    [--no-cpu-baseline] [--no-converge] [--no-warm] [--batched-only]
 
 Workload: 2D square lattice 32x32, n_nu = 64, n_om = 31, beta = 20,
 U in {1, 2, 4} (three instances, t = 0.1), Hubbard-atom inputs.  A step is
@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched uneven workload leg and print its JSON object")
     return ap.parse_args()
 
 
@@ -333,6 +335,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.batched_only:
+        print(json.dumps({"batched_uneven": batched_leg(B, log)}), flush=True)
+        return
     problems = I.workload_square32()
     insts = [B.make_instance(p, device=dev) for p in problems]
     prec = {"fp64": B.DF_FP64, "mixed": B.DF_FP32_REFINE, "fp32": B.DF_FP32}[args.prec]
