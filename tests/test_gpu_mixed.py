@@ -171,6 +171,30 @@ def test_adaptive_converges_to_fp64_fixed_point(B, use_graph):
         assert rel(a, b) <= TOL_MIXED
 
 
+def test_adaptive_at_large_n_nu(B):
+    """n_nu = 96 and 128: the FP32 phase runs the FP32 ladder of those sizes
+    (six and eight waves), the FP64 phase the certified FP64 kernels; the
+    converged Sigma~ is the FP64 path's."""
+    import torch
+    probs = [I.atomic_limit_problem(3, 4, 96, 3, 10.0, 2.0, I.T_REMAP_3D),
+             I.atomic_limit_problem(2, 4, 128, 3, 10.0, 2.0, 0.1)]
+    assert B.df_ladder_variant(96, B.DF_FP32) == "fp32"
+    assert B.df_ladder_variant(128, B.DF_FP32) == "fp32"
+    out = {}
+    for prec in (B.DF_FP64, B.DF_ADAPTIVE):
+        insts = [B.make_instance(p) for p in probs]
+        ws = B.workspace(insts)
+        print(f"adaptive large n_nu, prec {prec}", flush=True)
+        code, iters, d = B.df_iterate(insts, ws, B.make_opts(prec=prec, mix=0.5, tol=1e-11,
+                                                             max_iter=300, use_graph=1,
+                                                             switch_tol=1e-5))
+        torch.cuda.synchronize()
+        assert max(d) < 1e-11
+        out[prec] = [host(x.sigma) for x in insts]
+    for a, b in zip(out[B.DF_ADAPTIVE], out[B.DF_FP64]):
+        assert rel(a, b) <= TOL_MIXED
+
+
 def test_adaptive_never_converges_in_fp32(B):
     """A switch threshold below tol must not let an instance stop on FP32 ladders."""
     import torch
