@@ -36,6 +36,8 @@ SHAPES = [
     (2, 16, 48, 9, 10.0, 2.0, 0.1),
     (2, 32, 64, 31, 20.0, 2.0, 0.1),     # the bench shape (sampled q)
     (4, 4, 16, 5, 8.0, 2.0, 0.1),        # 4D: 384 group elements
+    (3, 4, 96, 3, 10.0, 2.0, 0.182358),  # six-wave kernels (FP32 alone, FP64)
+    (2, 4, 128, 3, 10.0, 2.0, 0.1),      # eight-wave kernels
 ]
 
 
