@@ -172,11 +172,11 @@ class LadderResult:
     W: np.ndarray          # [2][n_om][n_nu][N]
     logdet: np.ndarray     # [2][n_om][N] complex
     status: np.ndarray     # [2][n_om][N] int8
-    lam: Optional[np.ndarray] = None   # [2][n_om][N] max Re eig(gamma chi) (diagnostic)
+    lam: Optional[np.ndarray] = None   # [2][n_om][N] max Re eig(gamma chi), or max |eig| (diagnostic)
 
 
 def ladder(gamma_dm: np.ndarray, chi: np.ndarray, with_eigs: bool = False,
-           mode: str = "auto") -> LadderResult:
+           mode: str = "auto", abs_eigs: bool = False) -> LadderResult:
     """Ladder for every (channel, Omega, q).
 
     mode "auto" applies the convergence-radius rule (R4); mode "fallback"
@@ -222,7 +222,8 @@ def ladder(gamma_dm: np.ndarray, chi: np.ndarray, with_eigs: bool = False,
             st[singular] = STATUS_SINGULAR
             status[c, im] = st
             if with_eigs:
-                lam[c, im] = np.max(np.real(np.linalg.eigvals(M)), axis=1)
+                ev = np.linalg.eigvals(M)
+                lam[c, im] = np.max(np.abs(ev) if abs_eigs else np.real(ev), axis=1)
     return LadderResult(W=W, logdet=logdet, status=status, lam=lam)
 
 

@@ -166,3 +166,21 @@ def test_g_lat_closed_form_used_by_the_kernel(nk, n_nu, beta):
     a = 1.0 / (p.delta[:, None] - p.eps[None, :])
     fp64 = a + a / gg * G / gg * a
     assert np.abs(fp64 - ref).max() > 1e-11 * np.abs(ref).max()
+
+
+def test_frak_g_at_nonzero_dual_self_energy():
+    """frak G of the susceptibility formula at Sigma~ != 0, with G~ from the dual
+    Dyson equation: since G~ / G~0 = 1 / (1 - G~0 Sigma~) and G~0 + g = G_D with
+    G_D = [1/g + Delta - eps]^-1 (eq. gd0), frak G = G_D / (1 - (G_D - g) Sigma~).
+    G_D is formed here from g, Delta and eps alone.  A swapped G~ / G~0 in the
+    ratio, or a wrong sign of Sigma~ in the dual Dyson equation, fails this."""
+    for seed in (21, 22, 23):
+        g, delta, eps, S, _, _ = _generic_inputs(seed)
+        G0 = O.dual_gf0(g, delta, eps)
+        G = O.dual_gf(G0, S)
+        fg = LT.frak_g(G, G0, g)
+        GD = 1.0 / (1.0 / g[:, None] + delta[:, None] - eps[None, :])
+        want = GD / (1.0 - (GD - g[:, None]) * S)
+        assert np.abs(fg - want).max() <= 1e-12 * np.abs(want).max()
+        # the swapped ratio G~0 (G~0 + g) / G~ differs at Sigma~ != 0
+        assert np.abs(G0 * (G0 + g[:, None]) / G - want).max() > 1e-3 * np.abs(want).max()

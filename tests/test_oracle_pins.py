@@ -97,6 +97,50 @@ def test_p3_gd0_identity_and_symmetries():
     assert np.allclose(G2, G2[:, (-np.arange(8)) % 8, :], rtol=1e-14)
 
 
+def test_dual_dyson_through_the_lattice_dyson_equation():
+    """eq. (dyson) checked through physics, not by restating it: the G~ of
+    O.dual_gf, put into the lattice Green's function of eq. (glat), must obey
+    the lattice Dyson equation G^-1 = i nu + mu - eps - Sigma that the paper
+    states between eqs. (sigma_lat) and (glat), with Sigma from eq. (sigma_lat)
+    (denominator 1 + g Sigma~, the reading that makes the stated relation hold
+    for the G~ of eqs. gd0 and dyson) and Sigma^DMFT = i nu + mu - Delta - 1/g.
+    Both are written out here.  Generic complex g, Delta, Sigma~ and real eps; a
+    wrong sign of Sigma~ or an inverted G~0 in the dual Dyson equation fails."""
+    rng = np.random.default_rng(31)
+    n_nu, N, mu, beta = 6, 10, 0.4, 2.5
+    c = lambda *sh: rng.standard_normal(sh) + 1j * rng.standard_normal(sh)
+    g, delta, eps, S = c(n_nu), c(n_nu), rng.standard_normal(N), 0.3 * c(n_nu, N)
+    G = O.dual_gf(O.dual_gf0(g, delta, eps), S)
+    nu = ((2 * I.fermionic_indices(n_nu) + 1) * math.pi / beta)[:, None]
+    gg, dd, ee = g[:, None], delta[:, None], eps[None, :]
+    a = 1.0 / (dd - ee)
+    G_lat = a + a * (1.0 / gg) * G * (1.0 / gg) * a                       # eq. (glat)
+    sigma_dmft = 1j * nu + mu - dd - 1.0 / gg
+    sigma_lat = S / (1.0 + gg * S) + sigma_dmft                           # eq. (sigma_lat)
+    lhs = G_lat * (1j * nu + mu - ee - sigma_lat)
+    assert np.abs(lhs - 1.0).max() <= 1e-11
+    # the opposite sign of Sigma~ in the dual Dyson equation breaks the relation
+    Gw = O.dual_gf(O.dual_gf0(g, delta, eps), -S)
+    lhs_w = (a + a * (1.0 / gg) * Gw * (1.0 / gg) * a) * (1j * nu + mu - ee - sigma_lat)
+    assert np.abs(lhs_w - 1.0).max() > 1e-2
+
+
+def test_leading_eigenvalue_of_a_rank_one_vertex():
+    """For gamma = u v^T the matrix gamma diag(chi) has the single nonzero
+    eigenvalue sum_j v_j chi_j u_j (closed form); the diagnostic returns its
+    real part when it is positive, else zero."""
+    rng = np.random.default_rng(41)
+    n_nu, N, n_om = 5, 7, 3
+    u = rng.standard_normal(n_nu) + 1j * rng.standard_normal(n_nu)
+    v = rng.standard_normal(n_nu) + 1j * rng.standard_normal(n_nu)
+    gam = np.zeros((2, n_om, n_nu, n_nu), dtype=complex)
+    gam[1, 1] = np.outer(u, v)
+    chi = rng.standard_normal((n_om, n_nu, N)) + 1j * rng.standard_normal((n_om, n_nu, N))
+    lam = O.leading_eigenvalue(gam, chi, 1, 1)
+    want = np.maximum(np.real(np.einsum("j,jq,j->q", v, chi[1], u)), 0.0)
+    assert np.allclose(lam, want, rtol=1e-10, atol=1e-12)
+
+
 def test_dyson_definition():
     rng = np.random.default_rng(3)
     G0 = rng.standard_normal((4, 9)) + 1j * rng.standard_normal((4, 9))
