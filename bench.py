@@ -194,7 +194,7 @@ def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None, acce
     return out
 
 
-KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}>", "gjb_o3": "k_ladder_gjb_f64_o3<{np}>",
+KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}, false>", "gjb_o3": "k_ladder_gjb_f64_o3<{np}, false>",
                  "gjb_o4": "k_ladder_gjb_f64_o4<{np}>",
                  "vector": "k_ladder_fp64<{np},...>", "mfma": "k_ladder_mfma_f64<{np}>",
                  "mixed": "k_ladder_mixed<{np}>", "mixed_o3": "k_ladder_mixed_o3<{np}>",
@@ -203,15 +203,24 @@ KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}>", "gjb_o3": "k_ladder_gjb_f64_o3
                  "fp32_o5": "k_ladder_fp32_o5<{np}>"}
 
 
+def kernel_symbol(variant: str, np_: int) -> str:
+    """Kernel of a variant name; persistent grids ("@p1", "@p2") run the
+    item-loop build of the same kernel."""
+    base, _, persist = variant.partition("@")
+    sym = KERNEL_SYMBOL[base].format(np=np_)
+    return sym.replace(", false>", ", true>") if persist else sym
+
+
 def roofline_of(prec, B, n_om, N, n_nu, lad_ms, n_inst=1):
     """Roofline of the ladder kernel per instance; lad_ms is the time per instance
     (launches fused over n_inst instances, as the loop runs them)."""
     flops_launch = 2 * n_om * N * ladder_flops(n_nu)
     variant = B.df_ladder_variant(n_nu, prec)
-    kernel_name = KERNEL_SYMBOL[variant].format(np=n_nu)
-    if variant in ("fp32", "fp32_o4", "fp32_o5"):
+    kernel_name = kernel_symbol(variant, n_nu)
+    base = variant.partition("@")[0]
+    if base in ("fp32", "fp32_o4", "fp32_o5"):
         peak = FP32_PEAK_TFLOPS
-    elif variant not in ("mixed", "mixed_o3", "mixed_o4"):
+    elif base not in ("mixed", "mixed_o3", "mixed_o4"):
         peak = FP64_PEAK_TFLOPS
     else:
         # The refined solve's own work per solve: the inverse and Z0 = X gamma in
@@ -262,7 +271,7 @@ def batched_leg(B, log):
     import numpy as np
     import torch
     from paper_1507_00895_amd import inputs as I
-    probs = I.batched_problems(I.draw_batched_params())
+    probs = I.batched_problems(I.batched_params())
     insts = [B.make_instance(p) for p in probs]
     ws = B.workspace(insts)
     s = torch.cuda.Stream()

@@ -281,7 +281,12 @@ def df_ladder_set_variant(n_nu: int, prec: int, name: str):
                                                                         name.encode()))
 
 
-LADDER_VARIANTS = ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4", "mixed_o4")
+LADDER_KERNELS = ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4", "fp32_o5",
+                  "gjb_o4", "mixed_o4")
+# every choice: a kernel build with one work-group per item, or (the FP64
+# certified builds with an item loop) a persistent grid of 1x / 2x the
+# resident work-groups
+LADDER_VARIANTS = LADDER_KERNELS + tuple(f"{k}@p{p}" for p in (1, 2) for k in ("gjb", "gjb_o3"))
 
 
 def df_autotune_reset():

@@ -21,6 +21,12 @@ constexpr size_t kAlign = 256;
 constexpr int kMixBlocks = 512;
 constexpr int kQueueBlocks = 2048;
 constexpr int kMaxClasses = 16;
+// Layout of the ints region: per kernel class the uncertified-queue length,
+// the near-queue length and kXcd item counters of persistent launches; then
+// per instance the count of its ladders outside the radius.
+constexpr int kIntsNear = kMaxClasses;
+constexpr int kIntsClaim = 2 * kMaxClasses;
+constexpr int kIntsInst = kIntsClaim + kMaxClasses * kXcd;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -118,7 +124,9 @@ Layout layout_of(const Shape &s, int slots) {
 struct Global {
     size_t table;                     // LadderInst[n_inst] (fused launches)
     size_t queue;                     // int[sum of items]: uncertified items
-    size_t ints;                      // int[kMaxClasses + n_inst]: queue lengths, outside counts
+    size_t near;                      // int[sum of items]: refined kernel's items near the instability
+    size_t ints;                      // int[kIntsInst + n_inst]: queue lengths, item counters,
+                                      // outside counts
     size_t diffs;                     // double[n_inst][2]: diff, non-finite flag
     size_t accdots;                   // double[n_inst][kAccMaxSlots] (Anderson)
     size_t total;
@@ -155,8 +163,10 @@ int make_plan(const df_inst_t *inst, int32_t n_inst, Plan *P, int accel = 0) {
     off = align_up(off + (size_t)n_inst * sizeof(LadderInst));
     g.queue = off;
     off = align_up(off + items * sizeof(int));
+    g.near = off;
+    off = align_up(off + items * sizeof(int));
     g.ints = off;
-    off = align_up(off + (size_t)(kMaxClasses + n_inst) * sizeof(int));
+    off = align_up(off + (size_t)(kIntsInst + n_inst) * sizeof(int));
     g.diffs = off;
     off = align_up(off + (size_t)n_inst * 2 * sizeof(double));
     g.accdots = off;
@@ -222,9 +232,14 @@ int env_variant() {
 }
 
 int default_variant(int n_nu, int prec) {
-    if (prec == DF_FP32_REFINE && ladder_mixed_padded_size(n_nu) != 0) return LV_MIXED_O3;
-    if (prec == DF_FP32 && ladder_mixed_padded_size(n_nu) != 0) return LV_FP32_O4;
-    if (prec == DF_FP32 && ladder_fp32_padded_size(n_nu) != 0) return LV_FP32;
+    if (prec == DF_FP32_REFINE) {
+        if (ladder_mixed_has_occ(n_nu, 3)) return LV_MIXED_O3;
+        return LV_MIXED;
+    }
+    if (prec == DF_FP32) {
+        if (ladder_fp32_has_occ(n_nu, 4)) return LV_FP32_O4;
+        return LV_FP32;
+    }
     if (ladder_gjb_has_occ3(n_nu)) return LV_GJB_O3;
     if (ladder_gjb_padded_size(n_nu) != 0) return LV_GJB;
     return LV_VECTOR;
@@ -238,40 +253,116 @@ int ladder_variant(int n_nu, int prec) {
     return default_variant(n_nu, prec);
 }
 
-// Instances that share a kernel build and its padded size are fused in one launch.
+// Instances that share a kernel build, its padded size and launch shape are
+// fused in one launch.
 int ladder_class(int n_nu, int prec) {
     const int v = ladder_variant(n_nu, prec);
     return v * 256 + variant_padded_size(v, n_nu);
 }
 
-// Launch the ladder for the items in a (single instance, or a fused table);
-// the certified kernels queue their uncertified items to the pivoting kernel.
-int launch_ladder_variant(int v, LadderArgs a, int *queue, int *qcount, hipStream_t st) {
+// Queues and counters of one kernel class in the workspace.
+struct ClassSlots {
+    int *queue, *queue_count;         // uncertified items -> pivoting kernel
+    int *near, *near_count;           // refined kernel: items near the instability -> FP64 kernel
+    int *claim;                       // kXcd item counters of a persistent launch
+};
+
+ClassSlots class_slots(void *ws, const Global &g, int cls, size_t queue_off) {
+    int *ints = at<int>(ws, g.ints);
+    ClassSlots c;
+    c.queue = at<int>(ws, g.queue) + queue_off;
+    c.near = at<int>(ws, g.near) + queue_off;
+    c.queue_count = ints + cls;
+    c.near_count = ints + kIntsNear + cls;
+    c.claim = ints + kIntsClaim + cls * kXcd;
+    return c;
+}
+
+// Work-groups of a persistent launch: p times the resident work-groups of
+// the build on the whole device, at most one per item.
+int persistent_grid(int v, int n_nu, int p, int n_items) {
+    int per_cu = 0;
+    switch (v) {
+        case LV_GJB: per_cu = ladder_gjb_occupancy(n_nu, 0); break;
+        case LV_GJB_O3: per_cu = ladder_gjb_occupancy(n_nu, 3); break;
+        case LV_GJB_O4: per_cu = ladder_gjb_occupancy(n_nu, 4); break;
+        case LV_MIXED: per_cu = ladder_mixed_occupancy(n_nu, 0); break;
+        case LV_MIXED_O3: per_cu = ladder_mixed_occupancy(n_nu, 3); break;
+        case LV_MIXED_O4: per_cu = ladder_mixed_occupancy(n_nu, 4); break;
+        case LV_FP32: per_cu = ladder_fp32_occupancy(n_nu, 0); break;
+        case LV_FP32_O4: per_cu = ladder_fp32_occupancy(n_nu, 4); break;
+        case LV_FP32_O5: per_cu = ladder_fp32_occupancy(n_nu, 5); break;
+        default: break;
+    }
+    static int cus = -1;
+    if (cus < 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            n = 0;
+        cus = n;
+    }
+    long g = (long)p * (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    if (g > n_items) g = n_items;
+    return g < 1 ? 1 : (int)g;
+}
+
+// Launch the ladder for the items in a (single instance, or a fused table)
+// with choice c (variant and launch shape).  The certified kernels queue their
+// uncertified items to the pivoting kernel; the refined kernel first queues
+// its items near the instability to the FP64 certified kernel, which queues
+// its own uncertified ones to the pivoting kernel.  The class's counters must
+// be zero before the call.
+int launch_ladder_variant(int c, LadderArgs a, const ClassSlots &q, hipStream_t st) {
+    const int v = choice_variant(c), p = choice_persist(c);
     switch (v) {
         case LV_VECTOR: HIPCHK(launch_ladder_fp64(a, st)); return DF_OK;
         case LV_MFMA: HIPCHK(launch_ladder_mfma_f64(a, st)); return DF_OK;
         default: break;
     }
-    a.queue = queue;
-    a.queue_count = qcount;
+    a.queue = q.queue;
+    a.queue_count = q.queue_count;
+    int grid = a.n_items;
+    if (p > 0) {
+        a.claim = q.claim;
+        grid = persistent_grid(v, a.n_nu, p, a.n_items);
+    }
+    const bool refined = (v == LV_MIXED || v == LV_MIXED_O3 || v == LV_MIXED_O4);
+    if (refined) {
+        a.near_queue = q.near;
+        a.near_count = q.near_count;
+    }
     switch (v) {
-        case LV_FP32: HIPCHK(launch_ladder_fp32(a, 0, st)); break;
-        case LV_FP32_O4: HIPCHK(launch_ladder_fp32(a, 4, st)); break;
-        case LV_FP32_O5: HIPCHK(launch_ladder_fp32(a, 5, st)); break;
-        case LV_MIXED: HIPCHK(launch_ladder_mixed(a, 0, st)); break;
-        case LV_MIXED_O3: HIPCHK(launch_ladder_mixed(a, 3, st)); break;
-        case LV_MIXED_O4: HIPCHK(launch_ladder_mixed(a, 4, st)); break;
-        case LV_GJB_O3: HIPCHK(launch_ladder_gjb_f64(a, 3, st)); break;
-        case LV_GJB_O4: HIPCHK(launch_ladder_gjb_f64(a, 4, st)); break;
-        default: HIPCHK(launch_ladder_gjb_f64(a, 0, st)); break;
+        case LV_FP32: HIPCHK(launch_ladder_fp32(a, 0, grid, st)); break;
+        case LV_FP32_O4: HIPCHK(launch_ladder_fp32(a, 4, grid, st)); break;
+        case LV_FP32_O5: HIPCHK(launch_ladder_fp32(a, 5, grid, st)); break;
+        case LV_MIXED: HIPCHK(launch_ladder_mixed(a, 0, grid, st)); break;
+        case LV_MIXED_O3: HIPCHK(launch_ladder_mixed(a, 3, grid, st)); break;
+        case LV_MIXED_O4: HIPCHK(launch_ladder_mixed(a, 4, grid, st)); break;
+        case LV_GJB_O3: HIPCHK(launch_ladder_gjb_f64(a, 3, grid, st)); break;
+        case LV_GJB_O4: HIPCHK(launch_ladder_gjb_f64(a, 4, grid, st)); break;
+        default: HIPCHK(launch_ladder_gjb_f64(a, 0, grid, st)); break;
+    }
+    const int qblocks = a.n_items < kQueueBlocks ? a.n_items : kQueueBlocks;
+    if (refined) {
+        // the near-instability items: FP64 certified kernel over the near queue
+        LadderArgs b = a;
+        b.claim = nullptr;
+        b.near_queue = nullptr;
+        b.near_count = nullptr;
+        b.in_queue = q.near;
+        b.in_count = q.near_count;
+        HIPCHK(launch_ladder_gjb_f64(b, ladder_gjb_has_occ3(a.n_nu) ? 3 : 0, qblocks, st));
     }
     LadderArgs b = a;
+    b.claim = nullptr;
+    b.near_queue = nullptr;
+    b.near_count = nullptr;
     b.queue = nullptr;
     b.queue_count = nullptr;
-    b.in_queue = queue;
-    b.in_count = qcount;
-    const int blocks = a.n_items < kQueueBlocks ? a.n_items : kQueueBlocks;
-    HIPCHK(launch_ladder_fp64_queue(b, blocks, st));
+    b.in_queue = q.queue;
+    b.in_count = q.queue_count;
+    HIPCHK(launch_ladder_fp64_queue(b, qblocks, st));
     return DF_OK;
 }
 
@@ -459,7 +550,7 @@ int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &ac
             d.w = inst[i].w ? inst[i].w : at<double>(ws, b + L.w);
             d.logdet = inst[i].logdet;
             d.status = inst[i].status;
-            d.count = at<int>(ws, P.g.ints) + kMaxClasses + i;
+            d.count = at<int>(ws, P.g.ints) + kIntsInst + i;
             d.n_nu = s.n_nu;
             d.n_om = s.n_om;
             d.N = s.N;
@@ -502,7 +593,7 @@ int queue_fused_iteration(const df_inst_t *inst, const Plan &P, const Fused &F,
         if (rc != DF_OK) return rc;
     }
     int *ints = at<int>(ws, P.g.ints);
-    HIPCHK(launch_zero_ints(ints, kMaxClasses + (int)P.shape.size(), st));
+    HIPCHK(launch_zero_ints(ints, kIntsInst + (int)P.shape.size(), st));
     for (size_t c = 0; c < F.cls.size(); ++c) {
         const FusedClass &k = F.cls[c];
         LadderArgs a{};
@@ -511,7 +602,7 @@ int queue_fused_iteration(const df_inst_t *inst, const Plan &P, const Fused &F,
         a.n_nu = k.n_nu;
         a.item0 = 0;
         a.n_items = k.items;
-        rc = launch_ladder_variant(k.variant, a, at<int>(ws, P.g.queue) + k.queue_off, ints + c, st);
+        rc = launch_ladder_variant(k.variant, a, class_slots(ws, P.g, (int)c, k.queue_off), st);
         if (rc != DF_OK) return rc;
     }
     for (int i : F.active) {
@@ -752,7 +843,7 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         Fused F;
         rc = build_fused(inst, P, act, pr, sym, ws, &F, st);
         if (rc != DF_OK) return rc;
-        HIPCHK(launch_zero_ints(ints, kMaxClasses + n_inst, st));
+        HIPCHK(launch_zero_ints(ints, kIntsInst + n_inst, st));
         for (size_t c = 0; c < F.cls.size(); ++c) {
             const FusedClass &k = F.cls[c];
             LadderArgs a{};
@@ -761,7 +852,7 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
             a.n_nu = k.n_nu;
             a.item0 = 0;
             a.n_items = k.items;
-            rc = launch_ladder_variant(k.variant, a, at<int>(ws, P.g.queue) + k.queue_off, ints + c, st);
+            rc = launch_ladder_variant(k.variant, a, class_slots(ws, P.g, (int)c, k.queue_off), st);
             if (rc != DF_OK) return rc;
         }
         if (sym)
@@ -779,7 +870,7 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         const size_t b = P.base[i];
         rc = stage_gamma_prep(inst[i], s, ws, b, L, st);
         if (rc != DF_OK) return rc;
-        HIPCHK(launch_zero_ints(ints, kMaxClasses + n_inst, st));
+        HIPCHK(launch_zero_ints(ints, kIntsInst + n_inst, st));
         LadderArgs a{};
         a.gdm = at<double>(ws, b + L.gdm);
         a.pdm = at<double>(ws, b + L.pdm);
@@ -790,7 +881,7 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         a.w = inst[i].w;
         a.logdet = inst[i].logdet;
         a.status = inst[i].status;
-        a.fallback_count = ints + kMaxClasses + i;
+        a.fallback_count = ints + kIntsInst + i;
         a.n_nu = s.n_nu;
         a.n_om = s.n_om;
         a.N = s.N;
@@ -804,7 +895,7 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
             a.im0 = s.im0;
             a.n_items = s.items_sym;
         }
-        rc = launch_ladder_variant(ladder_variant(s.n_nu, prec), a, at<int>(ws, P.g.queue), ints, st);
+        rc = launch_ladder_variant(ladder_variant(s.n_nu, prec), a, class_slots(ws, P.g, 0, 0), st);
         if (rc != DF_OK) return rc;
         if (sym) {
             rc = stage_sym_expand(s, ws, b, L, inst[i].w, inst[i].logdet, inst[i].status, st);
@@ -881,7 +972,7 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     for (int i = 0; i < n_inst; ++i) act.push_back(i);
     std::vector<double> last(n_inst, INFINITY);
     std::vector<double> hdiff(2 * (size_t)n_inst);
-    std::vector<int> hints(kMaxClasses + n_inst);
+    std::vector<int> hints(kIntsInst + n_inst);
     // ladder precision of each instance; DF_ADAPTIVE starts in FP32 and moves
     // an instance to FP64 (for good) once its diff falls below switch_tol
     const bool adaptive = opts->prec == DF_ADAPTIVE;
@@ -892,7 +983,8 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     bool rebuild = true;
     int it = 0;
     int result = DF_OK;
-    bool any_fallback = false;
+    // per instance: some ladder of its own last iteration fell back
+    std::vector<char> fell_back(n_inst, 0);
     while (it < opts->max_iter && !act.empty()) {
         if (rebuild) {
             cleanup();
@@ -996,11 +1088,10 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
             cleanup();
             return DF_E_HIP;
         }
-        any_fallback = false;
         std::vector<int> next;
         for (int i : act) {
             last[i] = hdiff[2 * i];
-            if (hints[kMaxClasses + i]) any_fallback = true;
+            fell_back[i] = hints[kIntsInst + i] != 0;
             if (hdiff[2 * i + 1] != 0.0 || !isfinite(hdiff[2 * i])) {
                 result = DF_E_NONFINITE;
                 continue;
@@ -1046,7 +1137,9 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
         for (int i = 0; i < n_inst; ++i)
             if (!(last[i] < opts->tol)) return DF_E_NOT_CONVERGED;
     }
-    return any_fallback ? DF_W_FALLBACK : DF_OK;
+    for (int i = 0; i < n_inst; ++i)
+        if (fell_back[i]) return DF_W_FALLBACK;
+    return DF_OK;
 }
 
 int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, void *ws,
@@ -1109,7 +1202,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
             d.gtr32 = at<float>(ws, b + L.gtr32);
             d.chi = chi;
             d.w = at<double>(ws, b + L.w);
-            d.count = ints + kMaxClasses + i;
+            d.count = ints + kIntsInst + i;
             d.n_nu = s.n_nu;
             d.n_om = s.n_om;
             d.N = s.N;
@@ -1134,18 +1227,18 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         // two passes over the candidates, each variant keeping its faster
         // pass: a variant timed right after the slow pivoting kernels (or
         // while clocks settle) is not ranked on that pass alone
-        float vms[LV_COUNT];
-        for (int v = 0; v < LV_COUNT; ++v) vms[v] = -1.f;
+        float vms[kChoices];
+        for (int v = 0; v < kChoices; ++v) vms[v] = -1.f;
         for (int pass = 0; pass < 2 && rc == DF_OK; ++pass)
-        for (int v = 0; v < LV_COUNT && rc == DF_OK; ++v) {
+        for (int v = 0; v < kChoices && rc == DF_OK; ++v) {
             if (!variant_supports(v, n_nu, prec)) continue;
             constexpr int kReps = 3;
             float ms = 0.f;
             for (int r = 0; r <= kReps && rc == DF_OK; ++r) {   // r = 0: untimed first launch
                 if (r == 1 && hipEventRecord(e0, st) != hipSuccess) rc = DF_E_HIP;
-                if (rc == DF_OK && launch_zero_ints(ints, kMaxClasses + n_inst, st) != hipSuccess)
+                if (rc == DF_OK && launch_zero_ints(ints, kIntsInst + n_inst, st) != hipSuccess)
                     rc = DF_E_HIP;
-                if (rc == DF_OK) rc = launch_ladder_variant(v, a, at<int>(ws, P.g.queue), ints, st);
+                if (rc == DF_OK) rc = launch_ladder_variant(v, a, class_slots(ws, P.g, 0, 0), st);
             }
             if (rc == DF_OK && (hipEventRecord(e1, st) != hipSuccess ||
                                 hipEventSynchronize(e1) != hipSuccess ||
@@ -1154,7 +1247,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
             if (rc == DF_OK && (vms[v] < 0.f || ms < vms[v])) vms[v] = ms;
         }
         int best = -1;
-        for (int v = 0; v < LV_COUNT; ++v)
+        for (int v = 0; v < kChoices; ++v)
             if (vms[v] >= 0.f && (best < 0 || vms[v] < vms[best])) best = v;
         if (rc == DF_OK && best >= 0) set_tuned_variant(prec, n_nu, best);
         }

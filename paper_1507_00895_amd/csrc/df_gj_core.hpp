@@ -24,6 +24,10 @@
 // tile (w, t) to G_w (A_tt^-1 for w = t).  This is the block form of the
 // in-place sweep: afterwards the tiles hold D^-1, and the scalar pivots
 // (stored in FP64) multiply to det D.
+//
+// Every function takes the thread index as an argument: the kernels pass an
+// opaque copy made per item, so that nothing derived from it is hoisted out
+// of a persistent work-group's item loop and held across the whole item.
 #pragma once
 
 #include "df_internal.hpp"
@@ -248,9 +252,10 @@ __device__ __forceinline__ double wave_sum(double x) {
 template <typename T, int NP>
 __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP / 16],
                                              const typename MT<T>::v4 (&Ci)[NP / 16],
-                                             GjShared<T, NP> &sh, int iters, double accept) {
+                                             GjShared<T, NP> &sh, int iters, double accept,
+                                             int tid) {
     constexpr int NT = NP / 16;
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
+    const int w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
     // step 0 starts from v = 1 without reading it (no barrier before it)
     double cw = INFINITY;
     for (int it = 0; it < iters; ++it) {
@@ -314,9 +319,9 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
 // pivot column and 1/p at the pivot, i.e. the in-place Gauss-Jordan step.
 template <typename T>
 __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename MT<T>::v4 &Xi,
-                                               cd *pivot) {
+                                               cd *pivot, int tid) {
     typedef cplx<T> ct;
-    const int l = threadIdx.x & 63, lj = l & 15, lg = l >> 4;
+    const int l = tid & 63, lj = l & 15, lg = l >> 4;
     cd pvl = {0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
@@ -364,11 +369,12 @@ template <int NM, int NO> __device__ __forceinline__ void interleave_mfma() {
 // indexing should the loop ever be rolled to save instruction cache.
 template <typename T, int NP>
 __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16],
-                                         typename MT<T>::v4 (&Ci)[NP / 16], GjShared<T, NP> &sh) {
+                                         typename MT<T>::v4 (&Ci)[NP / 16], GjShared<T, NP> &sh,
+                                         int tid) {
     constexpr int NT = NP / 16;
     typedef cplx<T> ct;
     typedef typename MT<T>::v4 v4;
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
+    const int w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (w == t) {
@@ -382,7 +388,7 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
             v4 &Xr = Cr[0];
             v4 &Xi = Ci[0];
             cd pvl;
-            gj_tile_invert<T>(Xr, Xi, &pvl);
+            gj_tile_invert<T>(Xr, Xi, &pvl, tid);
             if (l < 16) sh.pivv[16 * t + l] = pvl;
 #pragma unroll
             for (int r = 0; r < 4; ++r) sh.Xw[t][MT<T>::row(lg, r)][lj] = ct{Xr[r], Xi[r]};
@@ -509,13 +515,14 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
 // update operands, so it pays only where that fits the register budget.
 template <typename T, int NP>
 __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP / 16],
-                                         typename MT<T>::v4 (&Ci)[NP / 16], GjShared<T, NP> &sh) {
+                                         typename MT<T>::v4 (&Ci)[NP / 16], GjShared<T, NP> &sh,
+                                         int tid) {
     constexpr int NT = NP / 16;
     typedef cplx<T> ct;
     typedef typename MT<T>::v4 v4;
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
+    const int w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
     cd pvl = {0.0, 0.0};   // pivots of the inverted tile: lane s < 16 holds step s
-    if (w == 0) gj_tile_invert<T>(Cr[0], Ci[0], &pvl);
+    if (w == 0) gj_tile_invert<T>(Cr[0], Ci[0], &pvl, tid);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (w == t) {
@@ -597,7 +604,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 if (ahead) {
                     update(1, 2);
                     __builtin_amdgcn_sched_barrier(0);
-                    gj_tile_invert<T>(Cr[1], Ci[1], &pvl);
+                    gj_tile_invert<T>(Cr[1], Ci[1], &pvl, tid);
                     update(2, NT);
                     interleave_mfma<12 * (NT - 2), 20>();
                 } else {
@@ -650,7 +657,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 if (ahead) {
                     update(1, 2);
                     __builtin_amdgcn_sched_barrier(0);
-                    gj_tile_invert<T>(Cr[1], Ci[1], &pvl);
+                    gj_tile_invert<T>(Cr[1], Ci[1], &pvl, tid);
                     update(2, NT);
                     interleave_mfma<16 * (NT - 2), 28>();
                 } else {
@@ -674,16 +681,17 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
 // Dispatch: LA selects the look-ahead sweep (measured per build).
 template <typename T, int NP, bool LA>
 __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
-                                         typename MT<T>::v4 (&Ci)[NP / 16], GjShared<T, NP> &sh) {
-    if constexpr (LA) gj_sweep_lookahead<T, NP>(Cr, Ci, sh);
-    else gj_sweep_plain<T, NP>(Cr, Ci, sh);
+                                         typename MT<T>::v4 (&Ci)[NP / 16], GjShared<T, NP> &sh,
+                                         int tid) {
+    if constexpr (LA) gj_sweep_lookahead<T, NP>(Cr, Ci, sh, tid);
+    else gj_sweep_plain<T, NP>(Cr, Ci, sh, tid);
 }
 
 // log det from the scalar pivots (no row exchanges), by wave 0; returns the
 // status code (0 inside, 1 outside, 2 non-finite) to lane 0 of wave 0.
 template <int NP>
-__device__ __forceinline__ int gj_logdet(const cd *pivv, cd *out_logdet) {
-    const int l = threadIdx.x & 63;
+__device__ __forceinline__ int gj_logdet(const cd *pivv, cd *out_logdet, int tid) {
+    const int l = tid & 63;
     double lre = 0.0, lim = 0.0;
     for (int k = l; k < NP; k += 64) {
         const cd pv = pivv[k];

@@ -104,10 +104,14 @@ struct LadderArgs {
     int item0, n_items;              // items are (c, m, q), q fastest
     int *fallback_count;             // may be null: atomically counts status != 0
     const double *gtr;               // [2][n_om][n_nu][n_nu] gamma transposed (gjb kernel)
-    int *queue;                      // gjb: uncertified items are appended here
-    int *queue_count;                // gjb: queue length (zeroed before the launch)
-    const int *in_queue;             // pivoting kernel: process these items ...
+    int *queue;                      // certified kernels: uncertified items are appended here
+    int *queue_count;                // its length (zeroed before the launch)
+    int *near_queue;                 // refined kernel: items whose certificate bound is
+    int *near_count;                 // >= CERT_NEAR_MIXED go here for the FP64 kernel
+    const int *in_queue;             // queue launches: process these items ...
     const int *in_count;             // ... (count on the device) instead of item0 + block
+    int *claim;                      // persistent launches: per-XCD item counters [kXcd]
+                                     // (zeroed before the launch); null: static mapping
     const LadderInst *insts;         // non-null: fused launch over n_insts instances,
     int n_insts;                     // items are global; the fields above are resolved per item
     const float *gp32;               // FP32 ladder: (gamma, gamma_ij gamma_ji) pairs, FP32
@@ -200,11 +204,68 @@ struct SymExpandArgs {
 // round-robin over the eight XCDs, each with its own L2).  Give every XCD one
 // contiguous range of the n items instead, so that the neighbouring q of one
 // (channel, Om) - which share the cache lines of chi and W - meet in one L2.
+constexpr int kXcd = 8;
 __device__ __forceinline__ int xcd_item(int b, int n) {
-    constexpr int kXcd = 8;
     const int per = n / kXcd, rem = n % kXcd;
     const int x = b % kXcd, i = b / kXcd;
     return x * per + (x < rem ? x : rem) + i;
+}
+
+// Items of a certified ladder launch, handed to body(global item) one at a
+// time; uniform over the work-group, which may run several items in turn
+// (LDS is reused: a barrier separates them).  The body appears once, so the
+// compiler inlines it once.
+//   in_queue set: the device-side queue of another kernel, grid-stride.
+//   claim null:   XCD x's contiguous range (as xcd_item) split over the
+//                 work-groups on that XCD; with one work-group per item this
+//                 is exactly the mapping of xcd_item.
+//   claim set:    persistent work-groups take the next item of their XCD's
+//                 range from its counter, then help the other XCDs' ranges.
+// k counts the items this work-group has run; tries (thread 0 only) the XCD
+// ranges it found empty.  Contains barriers when claim is set.
+__device__ __forceinline__ int next_item(const LadderArgs &a, int k, int *tries, int *s_item) {
+    if (a.in_queue) {
+        const int u = (int)blockIdx.x + k * (int)gridDim.x;
+        return u < *a.in_count ? a.in_queue[u] : -1;
+    }
+    const int n = a.n_items, per = n / kXcd, rem = n % kXcd;
+    const int x = blockIdx.x % kXcd;
+    if (!a.claim) {
+        const int len = per + (x < rem ? 1 : 0), start = x * per + (x < rem ? x : rem);
+        const int wgs = ((int)gridDim.x - x + kXcd - 1) / kXcd;   // work-groups on XCD x
+        const int i = (int)blockIdx.x / kXcd + k * wgs;
+        return i < len ? a.item0 + start + i : -1;
+    }
+    if (threadIdx.x == 0) {
+        int item = -1;
+        while (*tries < kXcd) {
+            const int xx = (x + *tries) % kXcd;
+            const int len = per + (xx < rem ? 1 : 0);
+            const int c = atomicAdd(a.claim + xx, 1);
+            if (c < len) {
+                item = a.item0 + xx * per + (xx < rem ? xx : rem) + c;
+                break;
+            }
+            ++*tries;
+        }
+        *s_item = item;
+    }
+    __syncthreads();
+    const int item = *s_item;
+    __syncthreads();
+    return item;
+}
+
+template <typename F>
+__device__ __forceinline__ void for_each_item(const LadderArgs &a, F &&body) {
+    __shared__ int s_item;
+    int tries = 0;
+    for (int k = 0;; ++k) {
+        const int item = __builtin_amdgcn_readfirstlane(next_item(a, k, &tries, &s_item));
+        if (item < 0) break;
+        body(item);
+        __syncthreads();
+    }
 }
 
 // Lattice observables (df_lattice.hip)
@@ -247,19 +308,25 @@ hipError_t launch_ladder_fp64(const LadderArgs &a, hipStream_t s);
 // MFMA blocked Gauss-Jordan variant (n_nu <= 64)
 int ladder_mfma_padded_size(int n_nu);
 hipError_t launch_ladder_mfma_f64(const LadderArgs &a, hipStream_t s);
-// certified pivot-free blocked Gauss-Jordan (n_nu <= 128); occ = 3 selects the
-// build capped at three waves per SIMD (n_nu <= 64), 0 the compiler's budget
+// certified pivot-free blocked Gauss-Jordan (n_nu <= 128); occ = 3 / 4 select
+// the builds capped at three / four waves per SIMD (n_nu <= 64), 0 the
+// compiler's budget; grid: work-groups of the launch (n_items for one per
+// item; fewer with a.claim set for persistent work-groups, or a queue launch)
 int ladder_gjb_padded_size(int n_nu);
 bool ladder_gjb_has_occ3(int n_nu);
-hipError_t launch_ladder_gjb_f64(const LadderArgs &a, int occ, hipStream_t s);
-// mixed precision: FP32 certified sweep + one FP64 residual correction (n_nu <= 64)
+hipError_t launch_ladder_gjb_f64(const LadderArgs &a, int occ, int grid, hipStream_t s);
+int ladder_gjb_occupancy(int n_nu, int occ);   // resident work-groups per CU
+// mixed precision: FP32 certified sweep + one FP64 residual correction, and
+// the FP32 sweep alone (n_nu <= 128); occ as above (refined: 0, 3 up to 96,
+// 4 up to 64; FP32: 0, and 4, 5 up to 64)
 int ladder_mixed_padded_size(int n_nu);
 int ladder_fp32_padded_size(int n_nu);
-bool ladder_mixed_has_occ3(int n_nu);
-hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, hipStream_t s);
-// FP32 only, no refinement (same sizes as the mixed kernel); occ = 4 or 5
-// selects the build capped at that many waves per SIMD
-hipError_t launch_ladder_fp32(const LadderArgs &a, int occ, hipStream_t s);
+bool ladder_mixed_has_occ(int n_nu, int occ);
+bool ladder_fp32_has_occ(int n_nu, int occ);
+hipError_t launch_ladder_mixed(const LadderArgs &a, int occ, int grid, hipStream_t s);
+hipError_t launch_ladder_fp32(const LadderArgs &a, int occ, int grid, hipStream_t s);
+int ladder_mixed_occupancy(int n_nu, int occ);
+int ladder_fp32_occupancy(int n_nu, int occ);
 // pivoting kernel over a device-side queue of items (grid-stride, fixed grid)
 hipError_t launch_ladder_fp64_queue(const LadderArgs &a, int blocks, hipStream_t s);
 hipError_t launch_zero_ints(int *p, int n, hipStream_t s);

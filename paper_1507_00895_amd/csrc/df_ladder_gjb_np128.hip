@@ -1,0 +1,8 @@
+// FP64 certified ladder builds for n_nu padded to 128.
+#include "df_ladder_gjb.hpp"
+
+namespace df {
+
+DF_GJB_INSTANTIATE(128)
+
+}  // namespace df

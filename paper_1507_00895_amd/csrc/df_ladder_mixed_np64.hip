@@ -1,0 +1,8 @@
+// Refined (FP32 + FP64 residual) ladder builds for n_nu padded to 64.
+#include "df_ladder_mixed.hpp"
+
+namespace df {
+
+DF_MIXED_INSTANTIATE(64)
+
+}  // namespace df

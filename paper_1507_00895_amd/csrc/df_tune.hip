@@ -47,34 +47,50 @@ void load_locked() {
 
 }  // namespace
 
-const char *variant_name(int v) { return (v >= 0 && v < LV_COUNT) ? kNames[v] : "none"; }
+const char *variant_name(int c) {
+    // "name", "name@p1", "name@p2" for every variant, built once
+    static char names[kChoices][24];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int k = 0; k < kChoices; ++k) {
+            const int v = choice_variant(k), p = choice_persist(k);
+            if (p == 0) snprintf(names[k], sizeof names[k], "%s", kNames[v]);
+            else snprintf(names[k], sizeof names[k], "%s@p%d", kNames[v], p);
+        }
+    });
+    return (c >= 0 && c < kChoices) ? names[c] : "none";
+}
 
 int variant_from_name(const char *name) {
     if (!name) return -1;
-    for (int v = 0; v < LV_COUNT; ++v)
-        if (strcmp(name, kNames[v]) == 0) return v;
+    for (int c = 0; c < kChoices; ++c)
+        if (strcmp(name, variant_name(c)) == 0) return c;
     return -1;
 }
 
-int variant_padded_size(int v, int n_nu) {
+int variant_padded_size(int c, int n_nu) {
+    if (c < 0 || c >= kChoices) return 0;
+    const int v = choice_variant(c);
+    // persistent grids: the FP64 certified builds with an item loop
+    if (choice_persist(c) != 0 && v != LV_GJB && v != LV_GJB_O3) return 0;
     switch (v) {
         case LV_GJB: return ladder_gjb_padded_size(n_nu);
         case LV_GJB_O3:
         case LV_GJB_O4: return ladder_gjb_has_occ3(n_nu) ? ladder_gjb_padded_size(n_nu) : 0;
         case LV_VECTOR: return ladder_padded_size(n_nu);
         case LV_MFMA: return ladder_mfma_padded_size(n_nu);
-        case LV_MIXED: return ladder_mixed_padded_size(n_nu);
-        case LV_MIXED_O3:
-        case LV_MIXED_O4: return ladder_mixed_has_occ3(n_nu) ? ladder_mixed_padded_size(n_nu) : 0;
-        case LV_FP32: return ladder_fp32_padded_size(n_nu);
-        case LV_FP32_O4:
-        case LV_FP32_O5: return ladder_mixed_padded_size(n_nu);
+        case LV_MIXED: return ladder_mixed_has_occ(n_nu, 0) ? ladder_mixed_padded_size(n_nu) : 0;
+        case LV_MIXED_O3: return ladder_mixed_has_occ(n_nu, 3) ? ladder_mixed_padded_size(n_nu) : 0;
+        case LV_MIXED_O4: return ladder_mixed_has_occ(n_nu, 4) ? ladder_mixed_padded_size(n_nu) : 0;
+        case LV_FP32: return ladder_fp32_has_occ(n_nu, 0) ? ladder_fp32_padded_size(n_nu) : 0;
+        case LV_FP32_O4: return ladder_fp32_has_occ(n_nu, 4) ? ladder_fp32_padded_size(n_nu) : 0;
+        case LV_FP32_O5: return ladder_fp32_has_occ(n_nu, 5) ? ladder_fp32_padded_size(n_nu) : 0;
         default: return 0;
     }
 }
 
-int variant_prec(int v) {
-    switch (v) {
+int variant_prec(int c) {
+    switch (choice_variant(c)) {
         case LV_MIXED:
         case LV_MIXED_O3:
         case LV_MIXED_O4: return DF_FP32_REFINE;
@@ -85,15 +101,10 @@ int variant_prec(int v) {
     }
 }
 
-// A request is served by the variants of its own precision class; where that
-// class has no kernel for n_nu (the refined kernels stop at n_nu = 64, the
-// FP32 ones at 128), by the FP64 variants.
-bool variant_supports(int v, int n_nu, int prec) {
-    if (variant_padded_size(v, n_nu) == 0) return false;
-    const int vp = variant_prec(v);
-    if (vp == prec) return true;
-    const int own = prec == DF_FP32 ? ladder_fp32_padded_size(n_nu) : ladder_mixed_padded_size(n_nu);
-    return vp == DF_FP64 && prec != DF_FP64 && own == 0;
+// A request is served by the variants of its own precision class only (each
+// class has kernels for every n_nu <= 128).
+bool variant_supports(int c, int n_nu, int prec) {
+    return variant_padded_size(c, n_nu) != 0 && variant_prec(c) == prec;
 }
 
 int tuned_variant(int prec, int n_nu) {
@@ -103,10 +114,10 @@ int tuned_variant(int prec, int n_nu) {
     return it == g_table.end() ? -1 : it->second;
 }
 
-void set_tuned_variant(int prec, int n_nu, int v) {
+void set_tuned_variant(int prec, int n_nu, int c) {
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
-    g_table[{prec, n_nu}] = v;
+    g_table[{prec, n_nu}] = c;
 }
 
 void clear_tuned() {

@@ -24,15 +24,24 @@ enum LadderVariant {
     LV_COUNT = 11
 };
 
-const char *variant_name(int v);
+// A choice is a kernel variant and a launch shape: c = v + LV_COUNT * p, with
+// p = 0 one work-group per item, p = 1, 2 a persistent grid of p times the
+// resident work-groups, each taking items from its XCD's counter.  Its name is
+// the variant's, with "@p1" / "@p2" appended for the persistent shapes.
+constexpr int kPersistModes = 3;
+constexpr int kChoices = LV_COUNT * kPersistModes;
+inline int choice_variant(int c) { return c % LV_COUNT; }
+inline int choice_persist(int c) { return c / LV_COUNT; }
+
+const char *variant_name(int c);
 int variant_from_name(const char *name);          // -1 if unknown
-int variant_prec(int v);                            // precision class the variant delivers
-bool variant_supports(int v, int n_nu, int prec);   // serves requests of this n_nu and precision
-int variant_padded_size(int v, int n_nu);
+int variant_prec(int c);                            // precision class the variant delivers
+bool variant_supports(int c, int n_nu, int prec);   // serves requests of this n_nu and precision
+int variant_padded_size(int c, int n_nu);
 
 // tuned choice for (prec, n_nu), or -1
 int tuned_variant(int prec, int n_nu);
-void set_tuned_variant(int prec, int n_nu, int v);
+void set_tuned_variant(int prec, int n_nu, int c);
 void clear_tuned();
 int save_tune_cache();   // 0 on success or when no cache file is configured
 

@@ -163,7 +163,8 @@ def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     # defaults: the capped builds that measured fastest at n_nu = 64
     assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3"
     assert B.df_ladder_variant(64, B.DF_FP32_REFINE) == "mixed_o3"
-    assert B.df_ladder_variant(96, B.DF_FP32_REFINE) == "gjb"      # beyond the mixed kernel
+    assert B.df_ladder_variant(96, B.DF_FP32_REFINE) == "mixed_o3"  # refined kernel up to 128
+    assert B.df_ladder_variant(128, B.DF_FP32_REFINE) == "mixed"
     assert B.df_ladder_variant(128, B.DF_FP64) == "gjb"
     assert B.df_ladder_variant(64, B.DF_FP32) == "fp32_o4"
     assert B.df_ladder_variant(128, B.DF_FP32) == "fp32"            # FP32 alone up to 128
@@ -173,7 +174,16 @@ def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o4")
     assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o4"
     assert B.df_ladder_variant(62, B.DF_FP64) == "gjb_o3"            # keyed by exact n_nu
+    # persistent grids: the FP64 certified builds with an item loop
+    B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o3@p1")
+    assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3@p1"
+    B.df_ladder_set_variant(128, B.DF_FP64, "gjb@p2")
+    assert B.df_ladder_variant(128, B.DF_FP64) == "gjb@p2"
+    B.df_ladder_set_variant(64, B.DF_FP64, "gjb_o4")
     for bad in [(96, B.DF_FP64, "gjb_o3"), (128, B.DF_FP64, "gjb_o4"), (64, B.DF_FP64, "mixed"),
+                (64, B.DF_FP64, "gjb_o4@p1"), (64, B.DF_FP32, "fp32_o4@p1"),
+                (64, B.DF_FP64, "vector@p1"), (128, B.DF_FP32_REFINE, "mixed_o3"),
+                (128, B.DF_FP32_REFINE, "gjb"), (96, B.DF_FP32_REFINE, "gjb"),
                 (64, B.DF_FP32_REFINE, "vector"), (64, B.DF_FP32_REFINE, "fp32_o4"),
                 (96, B.DF_FP32_REFINE, "mixed_o4"), (64, B.DF_FP64, "mixed_o3"),
                 (64, B.DF_FP32, "mixed"), (64, B.DF_FP64, "fp32_o4"), (96, B.DF_FP32, "fp32_o4"),

@@ -297,13 +297,16 @@ def test_fused_convergence_matches_single_instance_runs(torch_dev):
 
 def test_batched_uneven_workload_full_size_sampled(torch_dev):
     """The batched uneven workload at full size: 64 seeded instances (D in {2,3},
-    2D 16^2..64^2, 3D 8^3..16^3, n_nu in {32, 64, 128}) in one fused iteration,
-    as a serving call would run them.  Per instance: G~ in full; W at q = 0 and
-    one seeded q against the oracle ladder; for one instance of each
-    (D, nk, n_nu) class also chi~ and Sigma~calc (from the GPU's W) in full."""
+    2D 16^2..64^2, 3D 8^3..16^3, n_nu in {32, 64, 128}, mu = U/2 + U[-0.5, 0.5]
+    with the atom's inputs off half filling, first-iteration leading eigenvalue
+    below 0.9) in one fused iteration, as a serving call would run them.  Per
+    instance: G~ in full; W at q = 0 and one seeded q against the oracle
+    ladder; for one instance of each (D, nk, n_nu) class also chi~ and
+    Sigma~calc (from the GPU's W) in full."""
     torch = torch_dev
     from paper_1507_00895_amd import binding as B
-    params = I.draw_batched_params()
+    params = I.batched_params()
+    assert sum(abs(q["mu"] - q["U"] / 2) > 1e-3 for q in params) >= 60
     probs = I.batched_problems(params)
     insts = [B.make_instance(p) for p in probs]
     ws = B.workspace(insts)
