@@ -164,6 +164,16 @@ int df_dual_gf(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
 int df_bubble(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes,
               df_stream_t stream);
 
+/* df_bubble for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * workspace argument and no allocation.  Its scratch, G~(r) of one instance,
+ * is a library-owned device array of 8 MiB per device (n_nu N <= 128 * 4096
+ * complex, which every supported shape meets; DF_E_WORKSPACE otherwise).
+ * Reads gd, writes chi, as df_bubble.  Every call on a device shares that
+ * device's array: calls that overlap in time on one device (two streams, two
+ * threads) race and must be ordered by the caller. */
+int df_bubble_noalloc(const df_inst_t *inst, int32_t n_inst, df_stream_t stream);
+
 /* eqs. (spin_symm), (dual_ladder), (lin_alg_inv) and the radius test; Gamma^(2) of
  * eq. (sd).  Reads gamma_uu, gamma_ud, chi.  Writes w and, when non-NULL, logdet
  * and status.  opts may be NULL (DF_FP64); DF_ADAPTIVE is rejected here

@@ -36,7 +36,7 @@ DF_ADAPTIVE = 3
 
 EXPORTED = ("df_workspace_size", "df_dual_gf", "df_bubble", "df_ladder_solve", "df_sigma",
             "df_iterate", "df_autotune", "df_ladder_variant", "df_ladder_set_variant",
-            "df_autotune_reset", "df_strerror", "df_version")
+            "df_autotune_reset", "df_strerror", "df_version", "df_bubble_noalloc")
 
 
 class DfInst(ctypes.Structure):
@@ -83,6 +83,7 @@ def load() -> ctypes.CDLL:
                                        ctypes.c_void_p]
     lib.df_ladder_solve.argtypes = [P(DfInst), ctypes.c_int32, P(DfOpts), ctypes.c_void_p,
                                     ctypes.c_size_t, ctypes.c_void_p]
+    lib.df_bubble_noalloc.argtypes = [P(DfInst), ctypes.c_int32, ctypes.c_void_p]
     lib.df_iterate.argtypes = [P(DfInst), ctypes.c_int32, P(DfOpts), P(ctypes.c_int32),
                                P(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.df_autotune.argtypes = [P(DfInst), ctypes.c_int32, P(DfOpts), ctypes.c_void_p,
@@ -239,6 +240,12 @@ def df_dual_gf(insts, ws, stream=None):
 def df_bubble(insts, ws, stream=None):
     return _check("df_bubble", load().df_bubble(_arr(insts), len(insts), _ptr(ws), ws.numel(),
                                                 _stream(stream)))
+
+
+def df_bubble_noalloc(insts, stream=None):
+    """df_bubble without a workspace (the library's own device scratch)."""
+    return _check("df_bubble_noalloc", load().df_bubble_noalloc(_arr(insts), len(insts),
+                                                                _stream(stream)))
 
 
 def df_ladder_solve(insts, ws, opts: Optional[DfOpts] = None, stream=None):

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -803,6 +804,70 @@ int df_bubble(const df_inst_t *inst, int32_t n_inst, void *ws, size_t ws_bytes, 
     for (int i = 0; i < n_inst; ++i) {
         const Shape &s = P.shape[i];
         double *gr = at<double>(ws, P.base[i] + P.lay[i].gr);
+        rc = stage_transform_gd(s, inst[i].gd, gr, st);
+        if (rc != DF_OK) return rc;
+        rc = stage_bubble(inst[i], s, gr, inst[i].chi, st);
+        if (rc != DF_OK) return rc;
+    }
+    return DF_OK;
+}
+
+}  // extern "C"
+
+// ---- df_bubble without a workspace --------------------------------------------
+// The one scratch buffer of df_bubble, G~(r) of one instance ([n_nu][N]
+// complex), lives in a file-scope device array: 8 MiB, the size at n_nu = 128
+// and N = 4096, so every supported shape fits.  Each device holds its own copy
+// for the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device.
+namespace {
+
+constexpr size_t kBubbleScratchBytes = (size_t)128 * 4096 * 16;
+__device__ __align__(256) unsigned char scratch[kBubbleScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// The scratch array's address on the current device, looked up once per device.
+int scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DF_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return DF_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DF_E_HIP;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return DF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int df_bubble_noalloc(const df_inst_t *inst, int32_t n_inst, df_stream_t stream) {
+    if (!inst || n_inst < 1) return DF_E_INVAL;
+    for (int i = 0; i < n_inst; ++i) {
+        Shape s;
+        const int rc = check_inst(inst[i], &s);
+        if (rc != DF_OK) return rc;
+        if (!inst[i].gd || !inst[i].chi) return DF_E_INVAL;
+        if ((size_t)s.n_nu * s.N * 16 > kBubbleScratchBytes) return DF_E_WORKSPACE;
+    }
+    void *scr = nullptr;
+    int rc = scratch_address(&scr);
+    if (rc != DF_OK) return rc;
+    rc = ensure_attrs();
+    if (rc != DF_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double *gr = static_cast<double *>(scr);
+    // instances in turn on one stream: each overwrites the whole G~(r) it reads
+    for (int i = 0; i < n_inst; ++i) {
+        Shape s;
+        (void)check_inst(inst[i], &s);
         rc = stage_transform_gd(s, inst[i].gd, gr, st);
         if (rc != DF_OK) return rc;
         rc = stage_bubble(inst[i], s, gr, inst[i].chi, st);

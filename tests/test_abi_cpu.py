@@ -199,6 +199,19 @@ def test_ladder_variant_choice_host_side(tmp_path, monkeypatch):
     assert B.df_ladder_variant(64, B.DF_FP64) == "gjb_o3"
 
 
+def test_bubble_noalloc_validates_before_any_gpu_work():
+    lib = B.load()
+    assert lib.df_bubble_noalloc(None, 1, None) == B.DF_E_INVAL
+    arr = (B.DfInst * 1)(_inst())
+    assert lib.df_bubble_noalloc(arr, 0, None) == B.DF_E_INVAL
+    bad = _inst()
+    bad.nk = 6
+    assert lib.df_bubble_noalloc((B.DfInst * 1)(bad), 1, None) == B.DF_E_UNSUPPORTED
+    nogd = _inst()
+    nogd.gd = None
+    assert lib.df_bubble_noalloc((B.DfInst * 1)(nogd), 1, None) == B.DF_E_INVAL
+
+
 def test_autotune_validates_before_any_gpu_work():
     lib = B.load()
     assert lib.df_autotune(None, 1, None, None, 0, None) == B.DF_E_INVAL
