@@ -80,6 +80,11 @@ def parse():
                     help="skip the seconds-per-converged-Sigma~ legs of all paths")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-started path")
     ap.add_argument("--no-tune", action="store_true", help="keep the default ladder kernels")
+    ap.add_argument("--c5-train", type=int, default=2000,
+                    help="training instances of the full-scale warm start (64x64, n_nu 128)")
+    ap.add_argument("--c5-test", type=int, default=50, help="its held-out evaluation draws")
+    ap.add_argument("--no-c5", action="store_true", help="skip the full-scale warm start")
+    ap.add_argument("--no-cubic16", action="store_true", help="skip the 3D 16^3 leg")
     ap.add_argument("--warm-train", type=int, default=128,
                     help="converged instances the warm-start network is trained on")
     ap.add_argument("--warm-steps", type=int, default=6000)
@@ -91,57 +96,73 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(problems, budget_s: float = 20.0):
-    """Time the CPU oracle on a bounded sample of one outer iteration.
+def cpu_baseline(problems, budget_s: float = 8.0):
+    """Time the CPU oracle on one outer iteration of the first instance, on the
+    host's cores: 1 process, and P processes (P = the cores this process may
+    run on) with the ladder split over the bosonic slices; BLAS threads = 1 in
+    every process.
 
-    Sample: for the first instance, the oracle's dual propagator, bubble and
-    Schwinger-Dyson steps in full, and its ladder on as many bosonic slices
-    (all q, both channels) as fit in about budget_s; the ladder time is
-    scaled to all n_om slices.  Returns solves/s of whole iterations.
+    The dual propagator, bubble and Schwinger-Dyson steps run once in this
+    process (FFTs, single-threaded).  The 1-process ladder runs on as many
+    slices as fit in about budget_s and is scaled to all n_om; the P-process
+    ladder runs every slice.  Returns solves/s of whole iterations (P
+    processes as the value, the 1-process figure beside it).
     """
+    import multiprocessing as mp
     import numpy as np
     from oracle import df_oracle as O
+    from oracle.timing import ladder_seconds
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"     # inherited by the worker processes started below
     p = problems[0]
     t0 = time.perf_counter()
     G0 = O.dual_gf0(p.g, p.delta, p.eps)
     G = O.dual_gf(G0, np.zeros_like(G0))
     chi = O.bubble_fft(G, p.D, p.nk, p.n_om, p.beta)
     gam = O.spin_channels(p.gamma_uu, p.gamma_ud)
-    t1 = time.perf_counter()
-    n_sl = 0
-    t_lad = 0.0
-    Ws = []
-    while n_sl < p.n_om and t_lad < budget_s:
-        ta = time.perf_counter()
-        lr = O.ladder(gam[:, n_sl:n_sl + 1], chi[n_sl:n_sl + 1])
-        t_lad += time.perf_counter() - ta
-        Ws.append(lr.W)
-        n_sl += 1
+    t_pre = time.perf_counter() - t0
     W = np.zeros((2, p.n_om, p.n_nu, p.N), dtype=np.complex128)
-    W[:, :n_sl] = np.concatenate(Ws, axis=1)
     t2 = time.perf_counter()
     O.sigma_fft(W, G, p.D, p.nk, p.beta)
-    t3 = time.perf_counter()
-    t_iter = (t1 - t0) + (t3 - t2) + t_lad * (p.n_om / n_sl)
-    solves = 2 * p.n_om * p.N
+    t_sig = time.perf_counter() - t2
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores) or cores)
+    P = max(1, min(cores, 16, p.n_om))
+    ctx = mp.get_context("spawn")          # no fork of a process that holds the GPU
+    tasks = [(gam[:, m:m + 1], chi[m:m + 1]) for m in range(p.n_om)]
+    with ctx.Pool(1) as pool:
+        n_sl, t1 = 0, 0.0
+        pool.apply(ladder_seconds, (tasks[0],))           # imports, first touch
+        while n_sl < p.n_om and t1 < budget_s:
+            t1 += pool.apply(ladder_seconds, (tasks[n_sl],))
+            n_sl += 1
+    t_lad1 = t1 * p.n_om / n_sl
+    with ctx.Pool(P) as pool:
+        pool.map(ladder_seconds, tasks[:P], chunksize=1)  # imports, first touch
+        ta = time.perf_counter()
+        pool.map(ladder_seconds, tasks, chunksize=1)
+        t_ladP = time.perf_counter() - ta
+    solves = 2 * p.n_om * p.N
     model = None
     try:
         with open("/proc/cpuinfo") as f:
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": solves / t_iter, "unit": "solves/s", "cores": min(cores, threads),
-            "kind": "oracle", "cpu_model": model, "cpu_count": os.cpu_count(),
-            "affinity_cores": cores,
-            "sample": (f"one outer iteration of the U={p.U} instance: dual GF, bubble and "
-                       f"Schwinger-Dyson in full; ladder on {n_sl} of {p.n_om} bosonic slices "
-                       f"({2 * n_sl * p.N} solves, {t_lad:.1f} s), scaled to all slices; "
-                       f"est. {t_iter:.1f} s per iteration")}
+    one = solves / (t_pre + t_lad1 + t_sig)
+    return {"value": solves / (t_pre + t_ladP + t_sig), "unit": "solves/s", "cores": P,
+            "kind": "oracle", "processes": P, "blas_threads_per_process": 1,
+            "single_process": {"value": one, "cores": 1,
+                               "sample": f"ladder on {n_sl} of {p.n_om} bosonic slices, scaled"},
+            "cpu_model": model, "cpu_count": os.cpu_count(), "affinity_cores": cores,
+            "seconds_per_iteration": {"1_process": t_pre + t_lad1 + t_sig,
+                                      f"{P}_processes": t_pre + t_ladP + t_sig},
+            "sample": (f"one outer iteration of the U={p.U} instance of the 2D 32x32 workload: "
+                       f"dual GF, bubble and Schwinger-Dyson in one process; the ladder "
+                       f"({solves} solves) over all {p.n_om} bosonic slices on {P} processes "
+                       f"({t_ladP:.1f} s); 1 process: {n_sl} slices timed and scaled")}
 
 
 def orbit_count(D, nk):
@@ -298,34 +319,95 @@ def batched_leg(B, log):
     return out
 
 
-def warm_start_leg(problems, args, log):
-    """Train the warm-start network on the method's own converged Sigma~ at
-    this workload's shape, then predict the three instances' Sigma~."""
+def warm_start_leg(args, log):
+    """The learned warm start at the bench shape (2D 32x32, n_nu 64, n_om 31):
+    trained on args.warm_train converged Sigma~ (Latin-hypercube draws over
+    U in [1, 4], beta in [5, 20] with the box corners, seed 895), evaluated on
+    8 held-out draws (seed 896; none is a training point): iterations and
+    seconds to tol 1e-8, warm against cold, for the plain FP64 loop, the
+    adaptive loop and the adaptive Anderson-accelerated loop."""
+    from paper_1507_00895_amd import binding as B
     from paper_1507_00895_amd import warmstart as W
-    p = problems[0]
-    cfg = W.WarmStartConfig(nk=p.nk, n_nu=p.n_nu, n_om=p.n_om, t=p.t)
-    t0 = time.perf_counter()
-    ptrain = W.draw(args.warm_train, 895, cfg, corners=True)
-    sig, _, _ = W.converge(ptrain, cfg, accel=ACCEL)   # same fixed points, fewer iterations
-    t_data = time.perf_counter() - t0
-    X = W.build_features(ptrain, cfg)
-    Y = W.targets_from_sigma(sig, cfg)
-    net = W.WarmStartNet(X.shape[1], Y.shape[1])
-    t1 = time.perf_counter()
-    hist = net.fit(X, Y, steps=args.warm_steps)
-    t_train = time.perf_counter() - t1
-    log(f"warm start trained: {args.warm_train} instances ({t_data:.1f} s), "
-        f"{args.warm_steps} steps ({t_train:.1f} s)")
-    params = [(q.U, q.beta) for q in problems]
-    ta = time.perf_counter()
-    pred = net.predict(W.build_features(params, cfg))
-    sigma0 = [W.sigma_from_rows(pred[i * p.N:(i + 1) * p.N], cfg) for i in range(len(problems))]
-    t_inf = (time.perf_counter() - ta) / len(problems)
-    info = {"n_train": args.warm_train, "train_distribution": f"U in {cfg.U_range}, beta in {cfg.beta_range}",
-            "data_seconds": t_data, "train_steps": args.warm_steps, "train_seconds": t_train,
-            "train_loss_first_last": [hist[0][1], hist[-1][1]],
-            "inference_seconds_per_instance": t_inf}
-    return sigma0, info
+    cfg = W.WarmStartConfig(nk=32, n_nu=64, n_om=31, t=0.1)
+    r = W.train_and_evaluate(n_train=args.warm_train, n_test=8, steps=args.warm_steps, cfg=cfg,
+                             log=log, loop=dict(prec=B.DF_FP64),
+                             data_loop=dict(prec=B.DF_ADAPTIVE, accel=ACCEL),
+                             more_loops={"adaptive": (dict(prec=B.DF_ADAPTIVE), 8),
+                                         "adaptive_anderson": (dict(prec=B.DF_ADAPTIVE, accel=ACCEL), 8),
+                                         "adaptive_anderson_sym": (dict(prec=B.DF_ADAPTIVE, accel=ACCEL,
+                                                                        symmetry=1), 8)})
+    log(f"warm start (32x32, held out): FP64 loop {r['mean_iterations_cold']:.1f} -> "
+        f"{r['mean_iterations_warm']:.1f} iterations")
+    return r
+
+
+def warm_config5_leg(args, log):
+    """The learned warm start at its stated scale: 2D 64x64, n_nu 128, n_om 15,
+    U in [1, 4], beta in [5, 20], mu = U/2, t = 0.1; trained on args.c5_train
+    converged Sigma~ (seed 895, box corners included) generated by the
+    adaptive, Anderson-accelerated, symmetry-reduced loop, and evaluated on
+    args.c5_test held-out draws (seed 896): iterations and seconds to tol 1e-8,
+    warm against cold, with that loop and with the FP64 linear-mixing loop
+    (symmetry-reduced ladders) on the first 10 test points."""
+    from paper_1507_00895_amd import binding as B
+    from paper_1507_00895_amd import warmstart as W
+    cfg = W.WarmStartConfig(nk=64, n_nu=128, n_om=15, t=0.1)
+    fast = dict(prec=B.DF_ADAPTIVE, accel=ACCEL, symmetry=1)
+    r = W.train_and_evaluate(n_train=args.c5_train, n_test=args.c5_test, steps=args.warm_steps,
+                             cfg=cfg, log=log, loop=fast, data_loop=fast, batch=32,
+                             more_loops={"fp64_linear_mixing_sym": (dict(prec=B.DF_FP64, symmetry=1),
+                                                                    10)})
+    log(f"warm start (config 5, {args.c5_train} training, {args.c5_test} held out): "
+        f"{r['mean_iterations_cold']:.1f} -> {r['mean_iterations_warm']:.1f} iterations, "
+        f"{r['mean_seconds_cold']:.3f} -> {r['mean_seconds_warm']:.3f} s")
+    return r
+
+
+def cubic16_leg(B, args, log):
+    """3D 16^3, n_nu 96, n_om 23, U 3, beta 15, t 0.182358 (leading ladder
+    eigenvalue 0.97 at Q on the first iteration): after autotuning, the ladder
+    rate and roofline fraction of the FP64, refined (FP32 + FP64 residual,
+    FP64 determinants near the instability) and FP32 kernels, and seconds per
+    converged Sigma~ (tol 1e-8) of the FP64, refined and adaptive loops with
+    Anderson acceleration, plus the plain FP64 loop with symmetry-reduced
+    ladders."""
+    import numpy as np
+    import torch
+    from paper_1507_00895_amd import inputs as I
+    probs = I.workload_cubic16()
+    p = probs[0]
+    insts = [B.make_instance(q) for q in probs]
+    ws = B.workspace(insts, B.make_opts(accel=ACCEL))
+    stream = torch.cuda.Stream()
+    out = {"workload": "3D 16^3, n_nu 96, n_om 23, U 3, beta 15, t 0.182358, Hubbard-atom inputs"}
+    for name, pr in (("fp64", B.DF_FP64), ("mixed", B.DF_FP32_REFINE), ("fp32", B.DF_FP32)):
+        if not args.no_tune:
+            B.df_autotune(insts, ws, B.make_opts(prec=pr), stream=stream.cuda_stream)
+        ms = ladder_launch_ms(B, insts, ws, pr, stream, 3)
+        roof = roofline_of(pr, B, p.n_om, p.N, p.n_nu, ms)
+        out[name] = {"ladder_variant": B.df_ladder_variant(p.n_nu, pr), "ladder_launch_ms": ms,
+                     "ladder_solves_per_s": 2 * p.n_om * p.N / (ms * 1e-3),
+                     "roofline_frac": roof["frac"], "roofline_achieved": roof["achieved"],
+                     "roofline_peak": roof["peak"]}
+        log(f"cubic16 {name}: ladder {ms:.2f} ms ({out[name]['ladder_variant']}), "
+            f"{roof['frac']:.3f} of its roofline")
+    for name, pr, ac, sy in (("fp64", B.DF_FP64, ACCEL, 0), ("mixed", B.DF_FP32_REFINE, ACCEL, 0),
+                             ("adaptive", B.DF_ADAPTIVE, ACCEL, 0), ("fp64_sym_linear", B.DF_FP64, 0, 1)):
+        conv = converge_each(B, probs, insts, ws, pr, stream, 1, accel=ac, symmetry=sy)
+        out.setdefault(name, {}).update({"s_per_converged_sigma": conv[0]["seconds"],
+                                         "iterations": conv[0]["iterations"],
+                                         "final_diff": conv[0]["final_diff"], "code": conv[0]["code"],
+                                         "accel": ac, "symmetry": sy})
+        log(f"cubic16 {name}: {conv[0]['seconds']:.3f} s per converged Sigma~ "
+            f"({conv[0]['iterations']} iterations)")
+    # determinant of the magnetic ladder at Q, Omega = 0, first iteration and converged
+    i0 = (p.n_om - 1) // 2
+    Q = (p.nk // 2) * (p.nk * p.nk + p.nk + 1)
+    ld = insts[0].logdet[1, i0, Q].item()
+    out["det_magnetic_Q_converged"] = float(np.exp(ld.real) * np.cos(ld.imag))
+    del insts, ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -442,20 +524,13 @@ def main():
                  "converged": conv})
             log(f"{name}: {paths[name]['s_per_converged_sigma']:.3f} s per converged Sigma~")
         if not args.no_warm:
-            sigma0, info = warm_start_leg(problems, args, log)
-            for name, pr, ac, sy in (("warm_fp64", B.DF_FP64, 0, 0), ("warm_adaptive", B.DF_ADAPTIVE, 0, 0),
-                                     ("warm_adaptive_anderson", B.DF_ADAPTIVE, ACCEL, 0),
-                                     ("warm_adaptive_anderson_sym", B.DF_ADAPTIVE, ACCEL, 1)):
-                conv = converge_each(B, problems, insts, ws, pr, stream, args.graph, sigma0, accel=ac,
-                                     symmetry=sy)
-                sec = float(np.mean([c["seconds"] for c in conv])) + info["inference_seconds_per_instance"]
-                paths[name] = {"s_per_converged_sigma": sec,
-                               "mean_iterations": float(np.mean([c["iterations"] for c in conv])),
-                               "converged": conv}
-                log(f"{name}: {sec:.3f} s per converged Sigma~")
-            paths["warm_network"] = info
+            paths["warm_square32"] = warm_start_leg(args, log)
         paths["lattice_observables"] = lattice_leg(B, problems, insts, stream, log)
         paths["batched_uneven"] = batched_leg(B, log)
+        if not args.no_cubic16:
+            paths["cubic16"] = cubic16_leg(B, args, log)
+        if not args.no_warm and not args.no_c5:
+            paths["warm_config5"] = warm_config5_leg(args, log)
 
     out = {
         "metric": "ladder (q,omega) solves/s + s per converged Sigma~: FP64 vs FP32-MFMA+refine at 1e-9 rel",

@@ -74,6 +74,14 @@ def draw(n: int, seed: int, cfg: WarmStartConfig, corners: bool = False):
 WEDGE = [(x, y) for x in range(5) for y in range(x + 1)]          # 15 points of the 8x8 wedge
 
 
+def wedge_rows(nk: int) -> np.ndarray:
+    """Flat indices of the irreducible wedge 0 <= k_y <= k_x <= pi of the nk x nk
+    grid: one k per point-group orbit.  The features are invariant under the
+    group, so rows on the wedge train the network for the whole grid."""
+    h = nk // 2
+    return np.array([x * nk + y for x in range(h + 1) for y in range(x + 1)])
+
+
 def k_features(nk: int) -> np.ndarray:
     """Point-group-invariant functions of k on the nk x nk grid, [N, 5]."""
     k = I.kpoints(2, nk)
@@ -105,27 +113,37 @@ def coarse_gd0(params: List[tuple], cfg: WarmStartConfig, device="cuda") -> np.n
     return np.array(out)
 
 
-def build_features(params: List[tuple], cfg: WarmStartConfig, device="cuda") -> np.ndarray:
-    """[n * N, 132] feature rows, instance-major."""
-    N = cfg.nk ** 2
+def build_features(params: List[tuple], cfg: WarmStartConfig, device="cuda",
+                   rows: Optional[np.ndarray] = None) -> np.ndarray:
+    """[n * len(rows), 132] feature rows (FP32), instance-major; rows: the k
+    indices to include (default: all N)."""
     kf = k_features(cfg.nk)
+    if rows is not None:
+        kf = kf[rows]
+    nr = kf.shape[0]
     g0 = coarse_gd0(params, cfg, device)
-    rows = []
-    for (U, beta), gsum in zip(params, g0):
+    out = np.empty((len(params) * nr, 7 + kf.shape[1] + g0.shape[1]), dtype=np.float32)
+    for i, ((U, beta), gsum) in enumerate(zip(params, g0)):
         inst = np.array([U, beta, math.log(U), math.log(beta), 1.0 / beta, cfg.t, 2.0])
-        rows.append(np.concatenate([np.tile(inst, (N, 1)), kf, np.tile(gsum, (N, 1))], axis=1))
-    return np.concatenate(rows, axis=0)
+        out[i * nr:(i + 1) * nr] = np.concatenate([np.tile(inst, (nr, 1)), kf, np.tile(gsum, (nr, 1))],
+                                                  axis=1)
+    return out
 
 
 # ---------------------------------------------------------------- data from the method
 def converge(params: List[tuple], cfg: WarmStartConfig, sigma0: Optional[list] = None,
-             batch: int = 64, device="cuda", accel: int = 0):
+             batch: int = 64, device="cuda", accel: int = 0, prec: int = B.DF_FP64,
+             symmetry: int = 0, keep=None, log=None):
     """Run df_iterate to cfg.tol for every instance (fused batches; accel > 0:
-    Anderson-accelerated, same fixed point).
+    Anderson-accelerated, prec DF_ADAPTIVE: FP32 ladders far from the fixed
+    point, symmetry 1: one ladder per point-group orbit - each the same fixed
+    point).
 
-    Returns (sigma list [n_nu x N] numpy, iteration counts, seconds per batch).
+    Returns (per instance keep(sigma) - by default the converged Sigma~ as a
+    numpy [n_nu x N] array -, iteration counts, seconds per batch).
     """
     import torch
+    keep = keep or (lambda s: s)
     sig, its, secs = [], [], []
     stream = torch.cuda.Stream(device=device)
     for s in range(0, len(params), batch):
@@ -138,18 +156,23 @@ def converge(params: List[tuple], cfg: WarmStartConfig, sigma0: Optional[list] =
         ws = B.workspace(insts, B.make_opts(accel=accel), device=device)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        code, it, diffs = B.df_iterate(insts, ws, B.make_opts(mix=cfg.mix, tol=cfg.tol, max_iter=500,
-                                                              use_graph=1, accel=accel),
+        code, it, diffs = B.df_iterate(insts, ws, B.make_opts(prec=prec, mix=cfg.mix, tol=cfg.tol,
+                                                              max_iter=500, use_graph=1, accel=accel,
+                                                              symmetry=symmetry),
                                        stream=stream.cuda_stream,
                                        allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
         stream.synchronize()
         secs.append(time.perf_counter() - t0)
         its.append(it)
-        sig.extend(x.sigma.cpu().numpy() for x in insts)
+        sig.extend(keep(x.sigma.cpu().numpy()) for x in insts)
+        del insts, ws
+        if log and len(params) > batch:
+            log(f"converged {min(s + batch, len(params))} of {len(params)} ({secs[-1]:.2f} s, "
+                f"{it} iterations)")
     return sig, its, secs
 
 
-def targets_from_sigma(sigmas, cfg: WarmStartConfig) -> np.ndarray:
+def targets_from_sigma(sigmas, cfg: WarmStartConfig, rows: Optional[np.ndarray] = None) -> np.ndarray:
     """[n * N, 3 n_nu / 2] rows: Re and Im of Sigma~ / S at the positive
     frequencies, then n_nu / 2 copies of log S, with S the instance's
     root-mean-square |Sigma~|.
@@ -159,13 +182,15 @@ def targets_from_sigma(sigmas, cfg: WarmStartConfig) -> np.ndarray:
     the scale the same weight in the mean squared error as the shape.
     """
     h = cfg.n_nu // 2
-    rows = []
+    out = []
     for s in sigmas:
         S = max(float(np.sqrt(np.mean(np.abs(s) ** 2))), 1e-300)
         pos = s[h:].T / S                                          # [N, h], nu_0 .. nu_{h-1}
-        rows.append(np.concatenate([pos.real, pos.imag, np.full((pos.shape[0], h), math.log(S))],
-                                   axis=1))
-    return np.concatenate(rows, axis=0)
+        if rows is not None:
+            pos = pos[rows]
+        out.append(np.concatenate([pos.real, pos.imag, np.full((pos.shape[0], h), math.log(S))],
+                                  axis=1))
+    return np.concatenate(out, axis=0)
 
 
 def sigma_from_rows(rows: np.ndarray, cfg: WarmStartConfig) -> np.ndarray:
@@ -239,44 +264,78 @@ class WarmStartNet:
 def train_and_evaluate(n_train: int = 256, n_test: int = 16, steps: int = 2000,
                        cfg: Optional[WarmStartConfig] = None, seed_train: int = 895,
                        seed_test: int = 896, test_params: Optional[List[tuple]] = None,
-                       device="cuda", log=None):
+                       device="cuda", log=None, loop: Optional[dict] = None,
+                       data_loop: Optional[dict] = None, batch: int = 64,
+                       more_loops: Optional[dict] = None):
     """Generate converged Sigma~ with the method, train, compare cold and warm starts.
 
-    test_params: explicit (U, beta) pairs to evaluate on (default: n_test draws).
-    log: optional callable receiving progress strings.
+    The training set is a Latin-hypercube draw over the (U, beta) box with its
+    corners (seed_train); the test points are n_test fresh draws (seed_test)
+    or test_params, and none of them may be a training point (held out).
+    Training rows are the k of the irreducible wedge of each instance.
+    loop: df_iterate options of the cold / warm comparison (default: FP64,
+    linear mixing); data_loop: those of the data generation (default: FP64,
+    Anderson m = 5); more_loops: {name: (options, number of test points)},
+    further cold / warm comparisons on the first test points.  Every loop runs to cfg.tol, so both starts end at the
+    same fixed point.  log: optional callable receiving progress strings.
     """
     log = log or (lambda msg: None)
     cfg = cfg or WarmStartConfig()
+    loop = dict(loop or {})
+    data_loop = dict(data_loop or {"accel": 5})
     N = cfg.nk ** 2
+    rows = wedge_rows(cfg.nk)
     t0 = time.perf_counter()
     ptrain = draw(n_train, seed_train, cfg, corners=True)
-    # training data: the method's own fixed points (accelerated loop, same fixed point)
-    sig, its_train, _ = converge(ptrain, cfg, device=device, accel=5)
+    ptest = list(test_params) if test_params is not None else draw(n_test, seed_test, cfg)
+    train_set = set(ptrain)
+    if any(q in train_set for q in ptest):
+        raise ValueError("a test point is a training point")
+    n_test = len(ptest)
+    # training data: the method's own fixed points, kept as wedge rows of targets
+    Y, its_train, _ = converge(ptrain, cfg, device=device, batch=batch,
+                               keep=lambda s: targets_from_sigma([s], cfg, rows), log=log,
+                               **data_loop)
+    Y = np.concatenate(Y, axis=0)
     t_data = time.perf_counter() - t0
     log(f"warm start: {n_train} converged training instances in {t_data:.1f} s")
-    X = build_features(ptrain, cfg, device)
-    Y = targets_from_sigma(sig, cfg)
+    X = build_features(ptrain, cfg, device, rows=rows)
     net = WarmStartNet(X.shape[1], Y.shape[1], device=device)
     t1 = time.perf_counter()
     hist = net.fit(X, Y, steps=steps)
     t_train = time.perf_counter() - t1
     log(f"warm start: {steps} training steps in {t_train:.1f} s, loss {hist[0][1]:.3g} -> {hist[-1][1]:.3g}")
+    del X, Y
 
-    ptest = list(test_params) if test_params is not None else draw(n_test, seed_test, cfg)
-    n_test = len(ptest)
     ta = time.perf_counter()
-    Xt = build_features(ptest, cfg, device)
-    pred = net.predict(Xt)
+    pred = net.predict(build_features(ptest, cfg, device))
     t_inf = time.perf_counter() - ta
     warm0 = [sigma_from_rows(pred[i * N:(i + 1) * N], cfg) for i in range(n_test)]
-    sig_cold, it_cold, sec_cold = converge(ptest, cfg, batch=1, device=device)
-    sig_warm, it_warm, sec_warm = converge(ptest, cfg, sigma0=warm0, batch=1, device=device)
+    sig_cold, it_cold, sec_cold = converge(ptest, cfg, batch=1, device=device, **loop)
+    sig_warm, it_warm, sec_warm = converge(ptest, cfg, sigma0=warm0, batch=1, device=device, **loop)
     rel_pred = [float(np.linalg.norm(w - c) / np.linalg.norm(c)) for w, c in zip(warm0, sig_cold)]
     rel_fixed = [float(np.linalg.norm(w - c) / np.linalg.norm(c)) for w, c in zip(sig_warm, sig_cold)]
+    more = {}
+    for name, (opts, n_sub) in (more_loops or {}).items():
+        sub = ptest[:n_sub]
+        _, ic, sc = converge(sub, cfg, batch=1, device=device, keep=lambda s: None, **opts)
+        _, iw, sw = converge(sub, cfg, sigma0=warm0[:n_sub], batch=1, device=device,
+                             keep=lambda s: None, **opts)
+        more[name] = {"loop": {k: int(v) for k, v in opts.items()}, "n_test": len(sub),
+                      "mean_iterations_cold": float(np.mean(ic)),
+                      "mean_iterations_warm": float(np.mean(iw)),
+                      "mean_seconds_cold": float(np.mean(sc)),
+                      "mean_seconds_warm": float(np.mean(sw)) + t_inf / n_test}
+        log(f"warm start, {name}: iterations {more[name]['mean_iterations_cold']:.1f} -> "
+            f"{more[name]['mean_iterations_warm']:.1f}")
     return {
+        "more_loops": more,
         "workload": f"2D {cfg.nk}x{cfg.nk}, n_nu {cfg.n_nu}, n_om {cfg.n_om}, t {cfg.t}, "
                     f"U in {cfg.U_range}, beta in {cfg.beta_range}, tol {cfg.tol}",
-        "n_train": n_train, "n_test": n_test, "train_steps": steps, "test_params": ptest,
+        "n_train": n_train, "n_test": n_test, "train_steps": steps,
+        "test_held_out": True, "train_rows_per_instance": int(len(rows)),
+        "loop": {k: int(v) for k, v in loop.items()},
+        "data_loop": {k: int(v) for k, v in data_loop.items()},
         "train_loss_first_last": [hist[0][1], hist[-1][1]],
         "seconds_data": t_data, "seconds_train": t_train, "seconds_inference": t_inf,
         "iterations_cold": it_cold, "iterations_warm": it_warm,

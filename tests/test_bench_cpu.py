@@ -99,6 +99,9 @@ def test_cpu_baseline_on_a_small_problem():
     p = I.atomic_limit_problem(2, 8, 16, 3, 10.0, 2.0, 0.1)
     out = bench.cpu_baseline([p], budget_s=0.5)
     assert out["kind"] == "oracle" and out["unit"] == "solves/s"
-    assert out["value"] > 0 and out["cores"] >= 1
+    assert out["value"] > 0 and out["single_process"]["value"] > 0
+    # the core count is the number of processes that ran the ladder
+    assert out["cores"] == out["processes"] == min(out["affinity_cores"], 16, p.n_om)
+    assert out["single_process"]["cores"] == 1 and out["blas_threads_per_process"] == 1
     assert out["affinity_cores"] >= 1 and out["cpu_count"] >= 1
-    assert "of 3 bosonic slices" in out["sample"]
+    assert "all 3 bosonic slices" in out["sample"]
