@@ -121,12 +121,18 @@ struct LadderArgs {
 };
 
 // Fused launches: find the instance of a global item, fill the per-instance
-// fields of a, return the item's index within its instance.
+// fields of a, return the item's index within its instance.  The item is
+// uniform over the work-group and the table is read only: it is read through
+// the constant address space, so that the instance's fields arrive in scalar
+// registers (vector loads would hold them, and the item coordinates built
+// from them, in vector registers for the whole item).
+typedef __attribute__((address_space(4))) const LadderInst *ConstLadderInstPtr;
 __device__ __forceinline__ int resolve_item(LadderArgs &a, int item) {
     if (!a.insts) return item;
+    const ConstLadderInstPtr tab = (ConstLadderInstPtr)(const void *)a.insts;
     int k = 0;
-    while (k + 1 < a.n_insts && a.insts[k + 1].item0 <= item) ++k;
-    const LadderInst &d = a.insts[k];
+    while (k + 1 < a.n_insts && tab[k + 1].item0 <= item) ++k;
+    const auto &d = tab[k];
     a.gdm = d.gdm;
     a.pdm = d.pdm;
     a.gtr = d.gtr;
@@ -150,18 +156,20 @@ __device__ __forceinline__ int resolve_item(LadderArgs &a, int item) {
 // fastest.  Symmetry-reduced launches (qlist set): items are (c, m index >= im0,
 // k < n_q), k fastest, with q = qlist[k] - one q per point-group orbit and the
 // bosonic frequencies Omega >= 0; the others follow by symmetry (k_sym_expand).
+// The coordinates are uniform over the work-group: readfirstlane puts them
+// (and every address built from them) in scalar registers.  Integer division
+// is expanded with vector instructions, and without it the quotients stayed in
+// vector registers for the whole item.
 __device__ __forceinline__ void item_coords(const LadderArgs &a, int item, int *cm, int *q) {
     if (!a.qlist) {
-        *q = item % a.N;
-        *cm = item / a.N;
+        *q = __builtin_amdgcn_readfirstlane(item % a.N);
+        *cm = __builtin_amdgcn_readfirstlane(item / a.N);
         return;
     }
     const int k = item % a.n_q, r = item / a.n_q;
     const int nm = a.n_om - a.im0;
-    // the work-group's q is uniform: keep it (and every address built from it)
-    // in scalar registers, as in the full launches
     *q = __builtin_amdgcn_readfirstlane(a.qlist[k]);
-    *cm = (r / nm) * a.n_om + a.im0 + r % nm;
+    *cm = __builtin_amdgcn_readfirstlane((r / nm) * a.n_om + a.im0 + r % nm);
 }
 
 // Representative of q's orbit under the point group of the hypercubic lattice

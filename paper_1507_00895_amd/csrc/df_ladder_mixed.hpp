@@ -83,7 +83,7 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
     const int n_nu = a.n_nu, N = a.N;
     int q, cm;
     item_coords(a, item, &cm, &q);
-    const int im = cm % a.n_om;
+    const int im = __builtin_amdgcn_readfirstlane(cm % a.n_om);
     const size_t nn = (size_t)n_nu * n_nu;
     const double *gam = a.gdm + 2 * (size_t)cm * nn;
     const double *pm = a.pdm + 2 * (size_t)cm * nn;
