@@ -91,6 +91,13 @@ def parse():
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--traffic-table", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/ladder_traffic.json from the counter_collection.csv "
+                         "files of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "--profile-ladders --copy-calibration, then exit (no GPU needed)")
+    ap.add_argument("--profile-ladders", action="store_true",
+                    help="only the ladder launches of the main kernel builds (square 32x32 and "
+                         "cubic 16^3 workloads), for rocprofv3 runs")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched uneven workload leg and print its JSON object")
     return ap.parse_args()
@@ -410,8 +417,102 @@ def cubic16_leg(B, args, log):
     return out
 
 
+TRAFFIC_SOURCES = ["df_ladder_gjb.hpp", "df_ladder_mixed.hpp", "df_gj_core.hpp", "df_device.hpp",
+                   "df_internal.hpp"]
+
+
+def write_traffic_table(fetch_csv: str, write_csv: str) -> dict:
+    """profiles/ladder_traffic.json from two rocprofv3 counter_collection.csv
+    files: per ladder kernel and work-group count, FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch, averaged), each scaled by the factor that maps the same
+    counter on the plain 256 MiB device copy (the 256-work-group
+    __amd_rocclr_copyBuffer dispatch of --copy-calibration) to its 256 MiB;
+    with the hash of the kernel sources, so that the figures are used only
+    while those sources are unchanged."""
+    import csv
+    import hashlib
+    from collections import defaultdict
+
+    def per_kernel(path):
+        acc = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("df::", "")
+            wgs = int(r["Grid_Size"]) // int(r["Workgroup_Size"])
+            acc[(name, wgs)].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+    copy_mib = 256.0
+    f_copy = fetch[("__amd_rocclr_copyBuffer", 256)]
+    w_copy = write[("__amd_rocclr_copyBuffer", 256)]
+    ff, wf = copy_mib * 1024 / f_copy, copy_mib * 1024 / w_copy
+    kernels = {}
+    for (name, wgs), fk in fetch.items():
+        if "k_ladder" not in name or wgs < 1000 or (name, wgs) not in write:
+            continue
+        wk = write[(name, wgs)]
+        kernels[f"{name}@{wgs}"] = {"fetch_kib_raw": fk, "write_kib_raw": wk,
+                                    "fetch_bytes": fk * 1024 * ff, "write_bytes": wk * 1024 * wf,
+                                    "traffic_bytes": (fk * ff + wk * wf) * 1024}
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1507_00895_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    rec = {"workload": "bench.py --profile-ladders: 2D 32x32, n_nu 64, n_om 31 (three fused instances, "
+                       "190464 work-groups) and 3D 16^3, n_nu 96, n_om 23 (188416 work-groups)",
+           "source_files": TRAFFIC_SOURCES, "source_sha256_16": h.hexdigest()[:16],
+           "calibration": {"copy_bytes": int(copy_mib * 2 ** 20), "fetch_kib_raw": f_copy,
+                           "write_kib_raw": w_copy, "fetch_factor": ff, "write_factor": wf},
+           "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", "ladder_traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
+def profile_ladders(B, args, log):
+    """One untimed and three timed df_ladder_solve calls per kernel build, on
+    the 2D 32x32 workload (three fused instances: gjb_o4, gjb_o3, fp32_o4,
+    mixed_o3, gjb_o3@p1) and the 3D 16^3 one (gjb, fp32, mixed); with
+    --copy-calibration also one plain 256 MiB device copy.  For rocprofv3
+    (kernel times, counters); prints the HIP-event time per call."""
+    import torch
+    from paper_1507_00895_amd import inputs as I
+    stream = torch.cuda.Stream()
+    for wl, probs, cases in (("square32", I.workload_square32(),
+                              [(B.DF_FP64, "gjb_o4"), (B.DF_FP64, "gjb_o3"), (B.DF_FP32, "fp32_o4"),
+                               (B.DF_FP32_REFINE, "mixed_o3"), (B.DF_FP64, "gjb_o3@p1")]),
+                             ("cubic16", I.workload_cubic16(),
+                              [(B.DF_FP64, "gjb"), (B.DF_FP32, "fp32"), (B.DF_FP32_REFINE, "mixed")])):
+        insts = [B.make_instance(p) for p in probs]
+        ws = B.workspace(insts)
+        B.df_dual_gf(insts, ws)
+        B.df_bubble(insts, ws)
+        torch.cuda.synchronize()
+        for prec, name in cases:
+            B.df_ladder_set_variant(probs[0].n_nu, prec, name)
+            ms = ladder_launch_ms(B, insts, ws, prec, stream, 4)
+            log(f"{wl} {name}: {ms:.3f} ms per instance")
+        # one outer iteration (graph off): every kernel of the path in the trace
+        B.df_autotune_reset()
+        B.df_iterate(insts, ws, B.make_opts(mix=0.5, max_iter=1), stream=stream.cuda_stream)
+        stream.synchronize()
+        del insts, ws
+        torch.cuda.empty_cache()
+    if args.copy_calibration:
+        src = torch.ones(32 * 2 ** 20, dtype=torch.float64)
+        src = src.cuda()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+
 def main():
     args = parse()
+    if args.traffic_table:
+        rec = write_traffic_table(*args.traffic_table)
+        print(json.dumps({k: v["traffic_bytes"] for k, v in rec["kernels"].items()}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -426,6 +527,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.profile_ladders:
+        profile_ladders(B, args, log)
+        return
     if args.batched_only:
         print(json.dumps({"batched_uneven": batched_leg(B, log)}), flush=True)
         return
