@@ -19,7 +19,8 @@ namespace df {
 // the inverse FFT gr[n][r] = (1/N) sum_k e^{ikr} G~(k) (if gr_out).
 // With from_gd set, G~ is read from gd instead of being computed.
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dual_gf(DualGfArgs a) {
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_dual_gf(DualGfArgs a) {
     extern __shared__ cd lds[];
     cd *X = lds;
     cd *tw = lds + a.grid.N;
@@ -62,7 +63,8 @@ __global__ __launch_bounds__(256) void k_dual_gf(DualGfArgs a) {
 // chi_{m,n}(q) = -T FFT_r[ gr_n(-r) gr_{n+m}(r) ](q); zero when n+m leaves
 // the window.  One block per (n, m).
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_bubble(BubbleArgs a) {
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_bubble(BubbleArgs a) {
     extern __shared__ cd lds[];
     cd *X = lds;
     cd *tw = lds + a.grid.N;
@@ -94,16 +96,18 @@ __global__ __launch_bounds__(256) void k_bubble(BubbleArgs a) {
 //   v_{m,n} = IFFT_q[ 3 W^m_{m,n} + W^d_{m,n} ].
 // One block per (n, chunk); the accumulator lives in registers.
 // ------------------------------------------------------------------------
-constexpr int SIGMA_MAX_PER_THREAD = 16;   // N <= 4096 with 256 threads
-
-__global__ __launch_bounds__(256) void k_sigma_part(SigmaArgs a) {
+// (1024 threads: capped at 64 registers, so that two work-groups fit a CU)
+template <int NTH>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == 1024 ? 8 : 1)))
+void k_sigma_part(SigmaArgs a) {
+    constexpr int SIGMA_MAX_PER_THREAD = 4096 / NTH;   // N <= 4096
     extern __shared__ cd lds[];
     cd *X = lds;
     cd *tw = lds + a.grid.N;
     const Grid g = a.grid;
     const int n = blockIdx.x, chunk = blockIdx.y;
     const int nth = blockDim.x;
-    const int per = g.N / nth;                   // host guarantees N % 256 == 0 or N < 256
+    const int per = g.N / nth;                   // N is a power of two: N % nth == 0 or N < nth
     const int cnt = per > 0 ? per : (threadIdx.x < g.N ? 1 : 0);
     make_twiddles(tw, g);
     cd acc[SIGMA_MAX_PER_THREAD];
@@ -265,34 +269,48 @@ __global__ void k_zero_ints(int *p, int n) {
 // ------------------------------------------------------------------------
 static size_t fft_lds_bytes(const Grid &g) { return (size_t)(g.N + g.nk) * sizeof(cd); }
 
+// Threads per FFT work-group.  The FFT kernels keep N + nk complex doubles in
+// LDS, 66.5 KiB at N = 4096, so two work-groups fit a CU: 1024 threads each
+// then give 32 waves per CU (256 threads gave 8, and the LDS passes waited
+// on their latency).  Smaller grids keep 256 threads and more work-groups.
+static int fft_threads(const Grid &g) { return g.N >= 4096 ? 1024 : 256; }
+
 // The FFT kernels keep N + nk complex doubles in LDS: up to 66.5 KiB at
 // N = 4096, above the default 64 KiB limit of a launch.
 hipError_t set_fft_lds_limits() {
     const int bytes = (4096 + 64) * (int)sizeof(cd);
-    hipError_t e = hipFuncSetAttribute((const void *)k_dual_gf,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_bubble, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_sigma_part,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void *kernels[] = {(const void *)k_dual_gf<256>, (const void *)k_dual_gf<1024>,
+                             (const void *)k_bubble<256>, (const void *)k_bubble<1024>,
+                             (const void *)k_sigma_part<256>, (const void *)k_sigma_part<1024>};
+    hipError_t e = hipSuccess;
+    for (const void *k : kernels)
+        if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
 
 hipError_t launch_dual_gf(const DualGfArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_dual_gf, dim3(a.n_nu), dim3(256), fft_lds_bytes(a.grid), s, a);
+    if (fft_threads(a.grid) == 1024)
+        hipLaunchKernelGGL(k_dual_gf<1024>, dim3(a.n_nu), dim3(1024), fft_lds_bytes(a.grid), s, a);
+    else
+        hipLaunchKernelGGL(k_dual_gf<256>, dim3(a.n_nu), dim3(256), fft_lds_bytes(a.grid), s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_bubble(const BubbleArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_bubble, dim3(a.n_nu, a.n_om), dim3(256), fft_lds_bytes(a.grid), s, a);
+    if (fft_threads(a.grid) == 1024)
+        hipLaunchKernelGGL(k_bubble<1024>, dim3(a.n_nu, a.n_om), dim3(1024), fft_lds_bytes(a.grid), s, a);
+    else
+        hipLaunchKernelGGL(k_bubble<256>, dim3(a.n_nu, a.n_om), dim3(256), fft_lds_bytes(a.grid), s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_sigma_part(const SigmaArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_sigma_part, dim3(a.n_nu, a.n_chunks), dim3(256), fft_lds_bytes(a.grid),
-                       s, a);
+    if (fft_threads(a.grid) == 1024)
+        hipLaunchKernelGGL(k_sigma_part<1024>, dim3(a.n_nu, a.n_chunks), dim3(1024),
+                           fft_lds_bytes(a.grid), s, a);
+    else
+        hipLaunchKernelGGL(k_sigma_part<256>, dim3(a.n_nu, a.n_chunks), dim3(256),
+                           fft_lds_bytes(a.grid), s, a);
     return hipGetLastError();
 }
 
