@@ -261,6 +261,9 @@ def roofline_of(prec, B, n_om, N, n_nu, lad_ms, n_inst=1):
     return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": measured_traffic(kernel_name, 2 * n_om * N * n_inst, n_inst),
+            "traffic_source": "profiles/ladder_traffic.json: rocprofv3 FETCH_SIZE + WRITE_SIZE of "
+                              "this build and launch shape, scaled by a 256 MiB copy; null once "
+                              "the ladder sources differ from the profiled ones",
             "kernel": kernel_name, "variant": variant, "launch_ms": lad_ms,
             "algorithmic_flops_per_launch": flops_launch}
 

@@ -217,14 +217,19 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts,
 int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, void *ws,
                 size_t ws_bytes, df_stream_t stream);
 
-/* Name of the ladder kernel variant that calls for this n_nu and precision use
- * now ("gjb", "gjb_o3", "vector", "mfma", "mixed", "mixed_o3", "fp32", "fp32_o4", "fp32_o5", "gjb_o4", "mixed_o4"),
- * for prec DF_FP64, DF_FP32_REFINE or DF_FP32, written to the
- * host buffer name (NUL-terminated, name_len bytes at most).  Sizes: the
- * FP64 variants serve n_nu <= 128 ("gjb_o3" / "gjb_o4" up to 64); the refined
- * variants ("mixed*") n_nu <= 64; "fp32" n_nu <= 128, "fp32_o4" / "fp32_o5"
- * up to 64.  A precision class without a kernel for n_nu is served by the
- * FP64 variants. */
+/* Name of the ladder kernel choice that calls for this n_nu and precision use
+ * now, for prec DF_FP64, DF_FP32_REFINE or DF_FP32, written to the host buffer
+ * name (NUL-terminated, name_len bytes at most).  A choice is a kernel build
+ * ("gjb", "gjb_o3", "gjb_o4", "vector", "mfma" for FP64; "mixed", "mixed_o3",
+ * "mixed_o4" for the refined class; "fp32", "fp32_o4", "fp32_o5" for FP32
+ * alone), optionally with a launch shape: "@p1" / "@p2" = a persistent grid of
+ * 1x / 2x the resident work-groups taking items from per-XCD counters (for
+ * "gjb" and "gjb_o3"); without it, one work-group per item.  Sizes: every
+ * class serves n_nu <= 128; the builds capped at three waves per SIMD ("_o3")
+ * exist up to n_nu 64 (refined: 96), those at four or five ("_o4", "_o5") up
+ * to 64.  A choice always belongs to the requested precision class; the
+ * refined kernels hand their near-instability items to the FP64 kernel, and
+ * every certified kernel its uncertified items to "vector", within the call. */
 int df_ladder_variant(int32_t n_nu, int32_t prec, char *name, size_t name_len);
 
 /* Record a choice by hand, as df_autotune would: later calls for this n_nu and

@@ -13,7 +13,7 @@ For each point it records the wall time to convergence (tol 1e-10) and
 g = G~(i pi / beta, k = 0), and reports delta_g = |g_x - g_inf| / |g_inf|, with
 g_inf from a fit g_x = g_inf + a x^-p over the five largest points of the
 sweep (the paper extrapolates N_x -> infinity, eq. deltag, without saying
-how; a power law is what its Figs. 2-3 show).
+how; a power law is what its Figs. 1 and 2 show).
 
     python -m paper_1507_00895_amd.experiments --sweep om|nu|k|all [--repeat R]
 

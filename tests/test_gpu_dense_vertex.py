@@ -3,9 +3,10 @@ vertex measured by an impurity solver has no atomic-limit structure).
 
 gamma^uu and gamma^ud are seeded dense complex matrices, scaled so that the
 largest eigenvalue modulus of gamma^c diag(chi~) over all (c, Omega, q) is 0.8:
-every item is inside the convergence radius, but rho(|M|) is several times
-larger than max |lambda|, so the H-matrix certificate of the pivot-free kernels
-fails and the items go through the partial-pivoting kernel.  Parity with the
+every item is inside the convergence radius, but rho(|M|) exceeds max |lambda|
+(median about 0.46, up to 1.4), so the H-matrix certificate of the pivot-free
+kernels fails on part of the items (about 13 %), which then go through the
+partial-pivoting queue in the same call.  Parity with the
 oracle at each precision's bar, status bit-exact; the fraction of items with
 rho(|M|) < 0.999 (an upper bound on the certificate's pass rate, whose bound is
 never below rho(|M|)) and the ladder time are printed."""
