@@ -310,7 +310,7 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
 // accumulator layout (lane: column lj, rows MT<T>::row(lg, r)), by 16 scalar
 // Gauss-Jordan steps without pivoting: pivot by readlane, pivot column within
 // the lane's 16-lane row by DPP row_newbcast, pivot-row value of the lane's
-// column by one bpermute.  Lane s (s < 16) receives the pivot of step s.
+// column by one bpermute.  The 16 pivots go to pivrow[0..15] (LDS).
 //
 // Step s as one update of every element, x <- x - c'_i r'_j, with
 //   r'_j = r_j / p (j != s), r'_s = 1 + 1/p,   c'_i = c_i (i != s), c'_s = p - 1,
@@ -319,34 +319,44 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
 // pivot column and 1/p at the pivot, i.e. the in-place Gauss-Jordan step.
 template <typename T>
 __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename MT<T>::v4 &Xi,
-                                               cd *pivot, int tid) {
+                                               cd *pivrow, int tid) {
     typedef cplx<T> ct;
     const int l = tid & 63, lj = l & 15, lg = l >> 4;
-    cd pvl = {0.0, 0.0};
+    cd pvl = {0.0, 0.0};   // FP64: lane s < 16 collects the pivot of step s
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         const int ls = MT<T>::lg_of(s), rs = MT<T>::r_of(s);
         const int src = s + 16 * ls;
         const ct piv = {readlane_v(Xr[rs], src), readlane_v(Xi[rs], src)};
+        // FP32: the pivot goes to LDS from the lane that holds it, per step
+        // (measured faster there; in FP64 it costs registers, and the
+        // pivots are gathered in lanes and stored once)
+        if constexpr (sizeof(T) == 4) {
+            if (l == src) pivrow[s] = cd{(double)Xr[rs], (double)Xi[rs]};
+        }
         const int from = (lj + 16 * ls) << 2;
         const ct rr = {bperm_v(from, Xr[rs]), bperm_v(from, Xi[rs])};
         ct c[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) c[r] = {row_bcast_v(Xr[r], s), row_bcast_v(Xi[r], s)};
         const ct ip = recip_fast(piv);
-        ct rp = rr * ip;
-        if (lj == s) rp = ct{T(1) + ip.re, ip.im};
+        // r'_j = r_j / p; on the pivot column r_s = p, and (r_s + 1) / p = 1 + 1/p
+        const ct rp = ct{rr.re + ((lj == s) ? T(1) : T(0)), rr.im} * ip;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             ct cf = c[r];
-            if (r == rs && lg == ls) cf.re -= T(1);
+            if (r == rs) cf.re -= (lg == ls) ? T(1) : T(0);
             const ct x = fms(ct{Xr[r], Xi[r]}, cf, rp);
             Xr[r] = x.re;
             Xi[r] = x.im;
         }
-        if (l == s) pvl = cd{(double)piv.re, (double)piv.im};
+        if constexpr (sizeof(T) == 8) {
+            if (l == s) pvl = cd{(double)piv.re, (double)piv.im};
+        }
     }
-    *pivot = pvl;
+    if constexpr (sizeof(T) == 8) {
+        if (l < 16) pivrow[l] = pvl;
+    }
 }
 
 // Scheduling pattern for the current scheduling region: NM times one matrix
@@ -387,9 +397,7 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
             }
             v4 &Xr = Cr[0];
             v4 &Xi = Ci[0];
-            cd pvl;
-            gj_tile_invert<T>(Xr, Xi, &pvl, tid);
-            if (l < 16) sh.pivv[16 * t + l] = pvl;
+            gj_tile_invert<T>(Xr, Xi, sh.pivv + 16 * t, tid);
 #pragma unroll
             for (int r = 0; r < 4; ++r) sh.Xw[t][MT<T>::row(lg, r)][lj] = ct{Xr[r], Xi[r]};
         } else {
@@ -521,8 +529,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
     typedef cplx<T> ct;
     typedef typename MT<T>::v4 v4;
     const int w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
-    cd pvl = {0.0, 0.0};   // pivots of the inverted tile: lane s < 16 holds step s
-    if (w == 0) gj_tile_invert<T>(Cr[0], Ci[0], &pvl, tid);
+    if (w == 0) gj_tile_invert<T>(Cr[0], Ci[0], sh.pivv, tid);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (w == t) {
@@ -533,7 +540,6 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 for (int r = 0; r < 4; ++r)
                     sh.Rb[MT<T>::row(lg, r)][16 * c + lj] = ct{Cr[p][r], Ci[p][r]};
             }
-            if (l < 16) sh.pivv[16 * t + l] = pvl;
         }
         // every wave publishes its tile of column t: the inverse for w = t
 #pragma unroll
@@ -604,7 +610,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 if (ahead) {
                     update(1, 2);
                     __builtin_amdgcn_sched_barrier(0);
-                    gj_tile_invert<T>(Cr[1], Ci[1], &pvl, tid);
+                    gj_tile_invert<T>(Cr[1], Ci[1], sh.pivv + 16 * (t + 1), tid);
                     update(2, NT);
                     interleave_mfma<12 * (NT - 2), 20>();
                 } else {
@@ -657,7 +663,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 if (ahead) {
                     update(1, 2);
                     __builtin_amdgcn_sched_barrier(0);
-                    gj_tile_invert<T>(Cr[1], Ci[1], &pvl, tid);
+                    gj_tile_invert<T>(Cr[1], Ci[1], sh.pivv + 16 * (t + 1), tid);
                     update(2, NT);
                     interleave_mfma<16 * (NT - 2), 28>();
                 } else {
