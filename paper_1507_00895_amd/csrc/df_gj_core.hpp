@@ -210,9 +210,11 @@ template <typename T, int NP> struct GjShared {
 // Sum over the 16 lanes of the caller's DPP row, returned to all of them
 // (pairs by quad_perm, then rotations by 4 and 8 within the row).
 template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL,
-                                                      0xf, 0xf, false));
+    // every lane has a source for these controls; bound_ctrl lets the move
+    // fold into the add that consumes it
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
+__device__ __forceinline__ cf row16_sum(cf x);
 template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xf, 0xf, false);
@@ -234,6 +236,7 @@ __device__ __forceinline__ double row16_sum(double x) {
     return x;
 }
 __device__ __forceinline__ cd row16_sum(cd x) { return {row16_sum(x.re), row16_sum(x.im)}; }
+__device__ __forceinline__ cf row16_sum(cf x) { return {row16_sum(x.re), row16_sum(x.im)}; }
 // Sum over the wave, returned uniform: row sums, then the four row leaders.
 __device__ __forceinline__ double wave_sum(double x) {
     x = row16_sum(x);

@@ -9,6 +9,13 @@
 
 namespace df {
 
+// fermionic index into the vertex and bubble arrays; FULL: n_nu equals the
+// padded size and no index leaves the window
+template <bool FULL> __device__ __forceinline__ int clamp_nu(int j, int nm1) {
+    if constexpr (FULL) return j;
+    else return j < nm1 ? j : nm1;
+}
+
 struct DualGfArgs {
     Grid grid;
     int n_nu;
@@ -127,6 +134,16 @@ struct LadderArgs {
 // registers (vector loads would hold them, and the item coordinates built
 // from them, in vector registers for the whole item).
 typedef __attribute__((address_space(4))) const LadderInst *ConstLadderInstPtr;
+// n_nu of the instance that global item `item` belongs to (instances of
+// different n_nu can share a launch of one padded size)
+__device__ __forceinline__ int item_n_nu(const LadderArgs &a, int item) {
+    if (!a.insts) return a.n_nu;
+    const ConstLadderInstPtr tab = (ConstLadderInstPtr)(const void *)a.insts;
+    int k = 0;
+    while (k + 1 < a.n_insts && tab[k + 1].item0 <= item) ++k;
+    return tab[k].n_nu;
+}
+
 __device__ __forceinline__ int resolve_item(LadderArgs &a, int item) {
     if (!a.insts) return item;
     const ConstLadderInstPtr tab = (ConstLadderInstPtr)(const void *)a.insts;

@@ -59,19 +59,34 @@ template <int NP> struct PlainShared {
     GjShared<float, NP> gj;
 };
 
+// LDS of one item, one allocation per size and class (shared by the FULL and
+// the general item function)
+template <int NP, bool REFINE> struct MixedLds {
+    typename std::conditional<REFINE, MixedShared<NP>, PlainShared<NP>>::type sh;
+    cd ypart[NP];
+    cd tv[NP];
+    int s_flag;
+};
+template <int NP, bool REFINE> __device__ __forceinline__ MixedLds<NP, REFINE> &mixed_lds() {
+    __shared__ MixedLds<NP, REFINE> lds;
+    return lds;
+}
+
 // REFINE = false: the FP32 ladder alone, from FP32 copies of the vertex
 // arrays: D, t and Gamma_nn = sum_l X_nl gamma_ln with X = D^-1 from the FP32
 // sweep, all in FP32.  Relative error of order kappa n eps32, about 1e-6 for
-// certified items.
-template <int NP, bool REFINE>
+// certified items.  FULL: n_nu equals the padded size NP (no clamped index,
+// no masked padding).
+template <int NP, bool REFINE, bool FULL>
 __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
     constexpr int NT = NP / 16;
     typedef MT<float>::v4 f4;
     typedef MT<double>::v4 d4;
-    __shared__ typename std::conditional<REFINE, MixedShared<NP>, PlainShared<NP>>::type sh;
-    __shared__ cd ypart[NP];
-    __shared__ cd tv[NP];
-    __shared__ int s_flag;
+    MixedLds<NP, REFINE> &L = mixed_lds<NP, REFINE>();
+    auto &sh = L.sh;
+    cd *ypart = L.ypart;
+    cd *tv = L.tv;
+    int &s_flag = L.s_flag;
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -80,7 +95,7 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
     const int lg = l >> 4;
     LadderArgs a = a0;
     const int item = resolve_item(a, gitem);   // gitem: global item (fused launches)
-    const int n_nu = a.n_nu, N = a.N;
+    const int n_nu = FULL ? NP : a.n_nu, N = a.N;
     int q, cm;
     item_coords(a, item, &cm, &q);
     const int im = __builtin_amdgcn_readfirstlane(cm % a.n_om);
@@ -106,38 +121,42 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
 #pragma unroll
         for (int tc = 0; tc < NT; ++tc) {
             const int j = 16 * tc + lj;
-            const cd xd = ld(chi, (size_t)min(j, nm1) * N + q);
+            const cd xd = ld(chi, (size_t)clamp_nu<FULL>(j, nm1) * N + q);
             const cf xj = {(float)xd.re, (float)xd.im};
             fv4 gv[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                gv[r] = ld4f(gp, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+                gv[r] = ld4f(gp, (size_t)clamp_nu<FULL>(16 * w + MT<float>::row(lg, r), nm1) * n_nu + clamp_nu<FULL>(j, nm1));
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 16 * w + MT<float>::row(lg, r);
-                const bool in = (i < n_nu) && (j < n_nu);
+                const bool in = FULL || ((i < n_nu) && (j < n_nu));
                 const cf x = cf{gv[r].x, gv[r].y} * xj;
                 Cr[tc][r] = ((i == j) ? 1.f : 0.f) - (in ? x.re : 0.f);
                 Ci[tc][r] = in ? -x.im : 0.f;
                 tf[r] = fma_c(tf[r], in ? cf{gv[r].z, gv[r].w} : cf{0.f, 0.f}, xj);
             }
         }
+        // the row sums in FP32 too (the FP32 ladder's own error is far larger)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tp[r] = {(double)tf[r].re, (double)tf[r].im};
+        for (int r = 0; r < 4; ++r) {
+            const cf ts = row16_sum(tf[r]);
+            tp[r] = {(double)ts.re, (double)ts.im};
+        }
     } else {
     // t first, on its own, so that its loads do not sit beside the D tiles
 #pragma unroll
     for (int tc = 0; tc < NT; ++tc) {
         const int j = 16 * tc + lj;
-        const cd xj = ld(chi, (size_t)min(j, nm1) * N + q);
+        const cd xj = ld(chi, (size_t)clamp_nu<FULL>(j, nm1) * N + q);
         cd pv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            pv[r] = ld(pm, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+            pv[r] = ld(pm, (size_t)clamp_nu<FULL>(16 * w + MT<float>::row(lg, r), nm1) * n_nu + clamp_nu<FULL>(j, nm1));
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = 16 * w + MT<float>::row(lg, r);
-            const bool in = (i < n_nu) && (j < n_nu);
+            const bool in = FULL || ((i < n_nu) && (j < n_nu));
             tp[r] = fma_c(tp[r], in ? pv[r] : cd{0.0, 0.0}, xj);
         }
     }
@@ -145,23 +164,23 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
     for (int tc = 0; tc < NT; ++tc) {
         int j = 16 * tc + lj;
         asm volatile("" : "+v"(j));   // keeps each tile column's loads in place
-        const cd xj = ld(chi, (size_t)min(j, nm1) * N + q);
+        const cd xj = ld(chi, (size_t)clamp_nu<FULL>(j, nm1) * N + q);
         cd gv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            gv[r] = ld(gam, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+            gv[r] = ld(gam, (size_t)clamp_nu<FULL>(16 * w + MT<float>::row(lg, r), nm1) * n_nu + clamp_nu<FULL>(j, nm1));
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = 16 * w + MT<float>::row(lg, r);
-            const bool in = (i < n_nu) && (j < n_nu);
+            const bool in = FULL || ((i < n_nu) && (j < n_nu));
             const cd x = gv[r] * xj;
             Cr[tc][r] = (float)(((i == j) ? 1.0 : 0.0) - (in ? x.re : 0.0));
             Ci[tc][r] = (float)(in ? -x.im : 0.0);
         }
     }
-    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) tp[r] = row16_sum(tp[r]);
+    }
     if (lj == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) tv[16 * w + MT<float>::row(lg, r)] = tp[r];
@@ -216,19 +235,20 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
                 fv2 gv[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    gv[r] = ld2f(gtr, (size_t)min(row0 + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+                    gv[r] = ld2f(gtr, (size_t)clamp_nu<FULL>(row0 + MT<float>::row(lg, r), nm1) * n_nu + clamp_nu<FULL>(j, nm1));
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const bool in = (row0 + MT<float>::row(lg, r) < n_nu) && (j < n_nu);
+                    const bool in = FULL || ((row0 + MT<float>::row(lg, r) < n_nu) && (j < n_nu));
                     yf[r] = fma_c(yf[r], cf{Cr[tc][r], Ci[tc][r]},
                                   in ? cf{gv[r].x, gv[r].y} : cf{0.f, 0.f});
                 }
             }
             cd yp[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) yp[r] = {(double)yf[r].re, (double)yf[r].im};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) yp[r] = row16_sum(yp[r]);
+            for (int r = 0; r < 4; ++r) {
+                const cf ys = row16_sum(yf[r]);
+                yp[r] = {(double)ys.re, (double)ys.im};
+            }
             if (lj == 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) ypart[16 * w + MT<float>::row(lg, r)] = yp[r];
@@ -273,14 +293,14 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int e = tid + i * NP * 4, r = e / NP, c = e % NP;
-                gpre[i] = ld4f(gp, (size_t)min(16 * kt + r, nm1) * n_nu + min(c, nm1));
+                gpre[i] = ld4f(gp, (size_t)clamp_nu<FULL>(16 * kt + r, nm1) * n_nu + clamp_nu<FULL>(c, nm1));
             }
         };
         auto store_block = [&](int kt) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int e = tid + i * NP * 4, r = e / NP, c = e % NP;
-                const bool in = (16 * kt + r < n_nu) && (c < n_nu);
+                const bool in = FULL || ((16 * kt + r < n_nu) && (c < n_nu));
                 sh.z0.Gs[kt & 1][r][c] = in ? cf{gpre[i].x, gpre[i].y} : cf{0.f, 0.f};
             }
         };
@@ -340,7 +360,7 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
         constexpr int PW = 2;
         const int lp = 4 * (lj & 3) + (lj >> 2);   // perm(lj)
         const int ia = 16 * w + lp;
-        const size_t rowa = (size_t)min(ia, nm1) * n_nu;
+        const size_t rowa = (size_t)clamp_nu<FULL>(ia, nm1) * n_nu;
 #pragma unroll
         for (int p0 = 0; p0 < NT; p0 += PW) {
             d4 A1[PW], A2[PW], A3[PW];
@@ -352,11 +372,11 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
                 cd gv[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    gv[r] = ld(gam, (size_t)min(16 * w + MT<float>::row(lg, r), nm1) * n_nu + min(j, nm1));
+                    gv[r] = ld(gam, (size_t)clamp_nu<FULL>(16 * w + MT<float>::row(lg, r), nm1) * n_nu + clamp_nu<FULL>(j, nm1));
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = 16 * w + MT<float>::row(lg, r);
-                    const bool in = (i < n_nu) && (j < n_nu);
+                    const bool in = FULL || ((i < n_nu) && (j < n_nu));
                     const cf z = sh.Zs[i][zs_col<NP>(i, j)];
                     const double er = (in ? gv[r].re : 0.0) - (double)z.re;
                     const double ei = (in ? gv[r].im : 0.0) - (double)z.im;
@@ -373,8 +393,8 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
             {
                 int k = lg;
                 asm volatile("" : "+v"(k));
-                g_nx = ld(gam, rowa + min(k, nm1));
-                x_nx = ld(chi, (size_t)min(k, nm1) * N + q);
+                g_nx = ld(gam, rowa + clamp_nu<FULL>(k, nm1));
+                x_nx = ld(chi, (size_t)clamp_nu<FULL>(k, nm1) * N + q);
             }
 #pragma unroll
             for (int st_ = 0; st_ < 4 * NT; ++st_) {
@@ -384,8 +404,8 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
                 if (st_ + 1 < 4 * NT) {
                     int kn = k + 4;
                     asm volatile("" : "+v"(kn) : "v"(g0.re), "v"(xk.re));
-                    g_nx = ld(gam, rowa + min(kn, nm1));
-                    x_nx = ld(chi, (size_t)min(kn, nm1) * N + q);
+                    g_nx = ld(gam, rowa + clamp_nu<FULL>(kn, nm1));
+                    x_nx = ld(chi, (size_t)clamp_nu<FULL>(kn, nm1) * N + q);
                 }
                 __builtin_amdgcn_sched_barrier(0);   // the requests stay ahead of the products
                 // A operand M_ik = gamma_ik chi_k (FP64), B operand Z0_kj.  No mask:
@@ -470,31 +490,43 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
 template <int NP>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_ladder_mixed(LadderArgs a0) {
-    mixed_item<NP, true>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
+    if (item_n_nu(a0, gi) == NP) mixed_item<NP, true, true>(a0, gi);
+    else mixed_item<NP, true, false>(a0, gi);
 }
 template <int NP>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(3, 3)))
 void k_ladder_mixed_o3(LadderArgs a0) {
-    mixed_item<NP, true>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
+    if (item_n_nu(a0, gi) == NP) mixed_item<NP, true, true>(a0, gi);
+    else mixed_item<NP, true, false>(a0, gi);
 }
 template <int NP>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ladder_mixed_o4(LadderArgs a0) {
-    mixed_item<NP, true>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
+    if (item_n_nu(a0, gi) == NP) mixed_item<NP, true, true>(a0, gi);
+    else mixed_item<NP, true, false>(a0, gi);
 }
 template <int NP>
 __global__ __launch_bounds__(NP * 4) void k_ladder_fp32(LadderArgs a0) {
-    mixed_item<NP, false>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
+    if (item_n_nu(a0, gi) == NP) mixed_item<NP, false, true>(a0, gi);
+    else mixed_item<NP, false, false>(a0, gi);
 }
 template <int NP>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ladder_fp32_o4(LadderArgs a0) {
-    mixed_item<NP, false>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
+    if (item_n_nu(a0, gi) == NP) mixed_item<NP, false, true>(a0, gi);
+    else mixed_item<NP, false, false>(a0, gi);
 }
 template <int NP>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(5, 5)))
 void k_ladder_fp32_o5(LadderArgs a0) {
-    mixed_item<NP, false>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
+    if (item_n_nu(a0, gi) == NP) mixed_item<NP, false, true>(a0, gi);
+    else mixed_item<NP, false, false>(a0, gi);
 }
 
 // builds made for each size

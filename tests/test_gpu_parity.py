@@ -272,6 +272,38 @@ def test_fused_uneven_instances_match_oracle(torch_dev, prec):
         assert rel(host(x.sigma), r.sigma) <= tol, p.summary()
 
 
+SHARED_PADDED = [
+    (2, 4, 8, 3, 10.0, 2.0, 0.1),
+    (2, 4, 16, 3, 10.0, 2.5, 0.1),
+    (2, 8, 40, 3, 12.0, 1.5, 0.1),
+    (2, 8, 48, 3, 12.0, 2.0, 0.1),
+    (2, 4, 56, 5, 10.0, 3.0, 0.1),
+    (2, 4, 64, 3, 10.0, 2.0, 0.1),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_fused_launch_of_sizes_sharing_a_padded_size(torch_dev, prec):
+    """Instances whose n_nu differ but pad to the same size (8 and 16, 40 and 48,
+    56 and 64) share one fused ladder launch per padded size: each item must
+    take the mask-free path only when its own instance's n_nu is the padded
+    size.  W against the oracle at the precision's bar, status bit-exact."""
+    torch = torch_dev
+    from paper_1507_00895_amd import binding as B
+    probs = [I.atomic_limit_problem(*s) for s in SHARED_PADDED]
+    insts = [B.make_instance(p) for p in probs]
+    ws = B.workspace(insts)
+    B.df_dual_gf(insts, ws)
+    B.df_bubble(insts, ws)
+    B.df_ladder_solve(insts, ws, B.make_opts(prec=prec))
+    torch.cuda.synchronize()
+    tol = {0: TOL64, 1: 1e-9, 2: 2e-5}[prec]
+    for p, x in zip(probs, insts):
+        lr = O.ladder(O.spin_channels(p.gamma_uu, p.gamma_ud), host(x.chi))
+        assert np.array_equal(host(x.status), lr.status), p.summary()
+        assert rel(host(x.w), lr.W) <= tol, p.summary()
+
+
 def test_fused_convergence_matches_single_instance_runs(torch_dev):
     """Instances leave the fused graph as they converge; each ends where it would alone."""
     torch = torch_dev
