@@ -507,6 +507,7 @@ struct FusedClass {
     int t0, t1;                       // table range
     int items;                        // total items of the class
     size_t queue_off;                 // first queue slot (ints)
+    int full;                         // every member's n_nu equals the padded size
 };
 
 struct Fused {
@@ -536,6 +537,7 @@ int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &ac
         c.t0 = (int)F->table.size();
         c.items = 0;
         c.queue_off = qoff;
+        c.full = 1;
         for (int i : act) {
             if (ladder_class(P.shape[i].n_nu, prec[i]) != key) continue;
             const Shape &s = P.shape[i];
@@ -563,6 +565,7 @@ int build_fused(const df_inst_t *inst, const Plan &P, const std::vector<int> &ac
             }
             c.items += sym ? s.items_sym : s.items;
             c.n_nu = s.n_nu;
+            if (s.n_nu != ladder_gjb_padded_size(s.n_nu)) c.full = 0;
             c.variant = ladder_variant(s.n_nu, prec[i]);
             F->table.push_back(d);
             F->active.push_back(i);
@@ -601,6 +604,7 @@ int queue_fused_iteration(const df_inst_t *inst, const Plan &P, const Fused &F,
         a.insts = at<LadderInst>(ws, P.g.table) + k.t0;
         a.n_insts = k.t1 - k.t0;
         a.n_nu = k.n_nu;
+        a.full = k.full;
         a.item0 = 0;
         a.n_items = k.items;
         rc = launch_ladder_variant(k.variant, a, class_slots(ws, P.g, (int)c, k.queue_off), st);
@@ -915,6 +919,7 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
             a.insts = at<LadderInst>(ws, P.g.table) + k.t0;
             a.n_insts = k.t1 - k.t0;
             a.n_nu = k.n_nu;
+            a.full = k.full;
             a.item0 = 0;
             a.n_items = k.items;
             rc = launch_ladder_variant(k.variant, a, class_slots(ws, P.g, (int)c, k.queue_off), st);
@@ -950,6 +955,7 @@ int df_ladder_solve(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts
         a.n_nu = s.n_nu;
         a.n_om = s.n_om;
         a.N = s.N;
+        a.full = s.n_nu == ladder_gjb_padded_size(s.n_nu);
         a.item0 = 0;
         a.n_items = s.items;
         if (sym) {
@@ -1286,6 +1292,7 @@ int df_autotune(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, vo
         a.insts = at<LadderInst>(ws, P.g.table);
         a.n_insts = (int)table.size();
         a.n_nu = n_nu;
+        a.full = n_nu == ladder_gjb_padded_size(n_nu);
         a.item0 = 0;
         a.n_items = items;
         for (int prec : precs) {

@@ -125,6 +125,8 @@ struct LadderArgs {
     const float *gtr32;              // FP32 ladder: gamma transposed, FP32
     const int *qlist;                // non-null: symmetry-reduced items (see item_coords)
     int n_q, im0;
+    int full;                        // 1: every instance of the launch has n_nu equal to the
+                                     // padded size (the mask-free build runs)
 };
 
 // Fused launches: find the instance of a global item, fill the per-instance
@@ -134,16 +136,6 @@ struct LadderArgs {
 // registers (vector loads would hold them, and the item coordinates built
 // from them, in vector registers for the whole item).
 typedef __attribute__((address_space(4))) const LadderInst *ConstLadderInstPtr;
-// n_nu of the instance that global item `item` belongs to (instances of
-// different n_nu can share a launch of one padded size)
-__device__ __forceinline__ int item_n_nu(const LadderArgs &a, int item) {
-    if (!a.insts) return a.n_nu;
-    const ConstLadderInstPtr tab = (ConstLadderInstPtr)(const void *)a.insts;
-    int k = 0;
-    while (k + 1 < a.n_insts && tab[k + 1].item0 <= item) ++k;
-    return tab[k].n_nu;
-}
-
 __device__ __forceinline__ int resolve_item(LadderArgs &a, int item) {
     if (!a.insts) return item;
     const ConstLadderInstPtr tab = (ConstLadderInstPtr)(const void *)a.insts;

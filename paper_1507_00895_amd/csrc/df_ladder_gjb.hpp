@@ -21,33 +21,29 @@ constexpr double CERT_MAX_F64 = 0.999;
 // LOOP: the work-group may run several items in turn (a queue or a
 // persistent grid, for_each_item).  FULL: n_nu equals the padded size NP, so
 // no index is clamped and no padding is masked (measured 2-3 % faster than
-// the general path on the same items).
-// LDS of one item, one allocation per size (shared by the FULL and the
-// general item function)
-template <int NP> struct GjbLds {
-    GjShared<double, NP> sh;
-    cd yv[NP];
-    cd tv[NP];
-    int s_flag;
-};
-template <int NP> __device__ __forceinline__ GjbLds<NP> &gjb_lds() {
-    __shared__ GjbLds<NP> lds;
-    return lds;
-}
-
-template <int NP, bool LOOP, bool FULL>
-__device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem) {
+// the general path on the same items).  ITEMS = 2: the work-group holds two
+// items, one per half (k_ladder_gjb_f64_x2); both halves take every barrier,
+// so an uncertified item is not left early but carried through with its
+// results discarded, and `dummy` marks a half without an item of its own
+// (odd item counts), which computes a copy of the last item and writes
+// nothing.
+template <int NP, bool LOOP, bool FULL, int ITEMS = 1>
+__device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = false) {
     constexpr int NT = NP / 16;
     typedef MT<double>::v4 d4;
-    GjbLds<NP> &L = gjb_lds<NP>();
-    GjShared<double, NP> &sh = L.sh;
-    cd *yv = L.yv;
-    cd *tv = L.tv;
-    int &s_flag = L.s_flag;
+    __shared__ GjShared<double, NP> shv[ITEMS];
+    __shared__ cd yvv[ITEMS][NP];
+    __shared__ cd tvv[ITEMS][NP];
+    __shared__ int s_flagv[ITEMS];
+    const int half = (ITEMS == 2 && threadIdx.x >= NP * 4) ? 1 : 0;
+    GjShared<double, NP> &sh = shv[half];
+    cd *yv = yvv[half];
+    cd *tv = tvv[half];
+    int &s_flag = s_flagv[half];
 
     // in an item loop, an opaque copy of the thread index per item (see
     // df_gj_core.hpp)
-    int tid = threadIdx.x;
+    int tid = threadIdx.x - half * (NP * 4);
     if constexpr (LOOP) asm volatile("" : "+v"(tid));
     const int w = tid >> 6;
     const int l = tid & 63;
@@ -118,10 +114,13 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem) {
         }
     }
 
-    const double cw = gj_certify<double, NP>(Cr, Ci, sh, CERT_ITERS, CERT_MAX_F64, tid);
+    const double cw = gj_certify<double, NP>(Cr, Ci, sh, CERT_ITERS, CERT_MAX_F64, tid,
+                                             ITEMS == 2 ? &shv[1 - half] : nullptr);
+    bool skip = dummy;   // no results of this half are written
     if (!(cw < CERT_MAX_F64)) {
-        if (tid == 0 && a.queue) a.queue[atomicAdd(a.queue_count, 1)] = gitem;
-        return;   // uniform: every thread of the work-group leaves here
+        if (tid == 0 && a.queue && !dummy) a.queue[atomicAdd(a.queue_count, 1)] = gitem;
+        if constexpr (ITEMS == 1) return;   // uniform: every thread of the work-group leaves here
+        else skip = true;
     }
 
     // look-ahead inversion up to NP = 96: at 96 it removes the spills (7.14 ->
@@ -135,9 +134,11 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem) {
         if (l == 0) {
             s_flag = stt;
             const size_t o = (size_t)cm * N + q;
-            if (a.logdet) st(a.logdet, o, ldv);
-            if (a.status) a.status[o] = (int8_t)stt;
-            if (stt != 0 && a.fallback_count) atomicAdd(a.fallback_count, 1);
+            if (!skip) {
+                if (a.logdet) st(a.logdet, o, ldv);
+                if (a.status) a.status[o] = (int8_t)stt;
+                if (stt != 0 && a.fallback_count) atomicAdd(a.fallback_count, 1);
+            }
         }
     }
     __syncthreads();
@@ -176,62 +177,78 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem) {
         }
     }
     __syncthreads();
-    for (int n = tid; n < n_nu; n += NP * 4) {
-        const cd tt = tv[n];
-        cd wv;
-        if (stt == 0) {
-            const cd y = yv[n];
-            wv = {y.re - 0.5 * tt.re, y.im - 0.5 * tt.im};
-        } else {
-            const cd gnn = ld(gam, (size_t)n * n_nu + n);
-            wv = {gnn.re + 0.5 * tt.re, gnn.im + 0.5 * tt.im};
+    if (!skip)
+        for (int n = tid; n < n_nu; n += NP * 4) {
+            const cd tt = tv[n];
+            cd wv;
+            if (stt == 0) {
+                const cd y = yv[n];
+                wv = {y.re - 0.5 * tt.re, y.im - 0.5 * tt.im};
+            } else {
+                const cd gnn = ld(gam, (size_t)n * n_nu + n);
+                wv = {gnn.re + 0.5 * tt.re, gnn.im + 0.5 * tt.im};
+            }
+            st(a.w, ((size_t)cm * n_nu + n) * N + q, wv);
         }
-        st(a.w, ((size_t)cm * n_nu + n) * N + q, wv);
-    }
 }
 
-// Items of an item-loop (LOOP) build: a queue's, or a persistent grid's
-// (the general path only: both paths in one loop body held more registers).
-template <int NP>
+// Items of an item-loop (LOOP) build: a queue's, or a persistent grid's.
+template <int NP, bool FULL>
 __device__ __forceinline__ void gjb_loop(const LadderArgs &a0) {
     for_each_item(a0, [&](int gitem) __attribute__((always_inline)) {
-        gjb_item<NP, true, false>(a0, gitem);
+        gjb_item<NP, true, FULL>(a0, gitem);
     });
 }
 
 // One work-group per item (dealt to the XCDs in contiguous ranges), or the
 // item loop.  (The one-item kernels call the item function with their argument
 // block directly: through a reference and a copy the compiler allocated more
-// registers and spilled.)
-#define DF_GJB_BODY(NP, LOOP)                                                   \
-    if constexpr (LOOP) gjb_loop<NP>(a0);                                       \
-    else {                                                                      \
-        const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);              \
-        if (item_n_nu(a0, gi) == NP) gjb_item<NP, false, true>(a0, gi);         \
-        else gjb_item<NP, false, false>(a0, gi);                                \
-    }
+// registers and spilled.)  FULL selects the mask-free build, for launches
+// whose instances all have n_nu equal to NP (LadderArgs::full); each kernel
+// holds one of the two paths, as one holding both needed more registers.
+#define DF_GJB_BODY(NP, LOOP, FULL)                                             \
+    if constexpr (LOOP) gjb_loop<NP, FULL>(a0);                                 \
+    else gjb_item<NP, false, FULL>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
 
 // Register budgets of the same kernel: the compiler's own (two work-groups
 // per CU at NP = 48, 64) and builds capped for three and four waves per SIMD
-// (NP <= 64; the four-wave build spills).  (At NP = 96 the capped build
-// spills and measured 25 % slower: not built.)  LOOP builds (the compiler's
-// budget and the three-wave cap) serve queue launches and persistent grids.
-template <int NP, bool LOOP>
+// (NP <= 64).  (At NP = 96 the capped build spills and measured 6-25 %
+// slower: not built.)  LOOP builds (the compiler's budget and the three-wave
+// cap) serve queue launches and persistent grids.
+template <int NP, bool LOOP, bool FULL>
 __global__ __launch_bounds__(NP * 4) void k_ladder_gjb_f64(LadderArgs a0) {
-    DF_GJB_BODY(NP, LOOP)
+    DF_GJB_BODY(NP, LOOP, FULL)
 }
-template <int NP, bool LOOP>
+template <int NP, bool LOOP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(3, 3)))
 void k_ladder_gjb_f64_o3(LadderArgs a0) {
-    DF_GJB_BODY(NP, LOOP)
+    DF_GJB_BODY(NP, LOOP, FULL)
 }
-template <int NP>
+template <int NP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ladder_gjb_f64_o4(LadderArgs a0) {
-    // the general path only: the mask-free one spills more under this cap
-    // (measured slower)
-    gjb_item<NP, false, false>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+    DF_GJB_BODY(NP, false, FULL)
 }
+
+// Two items per work-group (NP = 96): an item is six waves, and with six-wave
+// work-groups a CU held one work-group even where the registers allowed
+// three waves per SIMD (1.5 waves per SIMD measured); a twelve-wave
+// work-group of two items fills three per SIMD.  Items 2 p and 2 p + 1 of
+// the launch, p the XCD-mapped work-group index.
+template <int NP, bool FULL>
+__global__ __launch_bounds__(NP * 8) void k_ladder_gjb_f64_x2(LadderArgs a0) {
+    const int half = threadIdx.x >= NP * 4 ? 1 : 0;
+    const int k = 2 * xcd_item(blockIdx.x, gridDim.x) + half;
+    const bool dummy = k >= a0.n_items;
+    gjb_item<NP, false, FULL, 2>(a0, a0.item0 + (dummy ? a0.n_items - 1 : k), dummy);
+}
+
+// the launch of one build with the launch's FULL choice
+#define DF_LAUNCH_FULL(KERN, ...)                                                       \
+    do {                                                                                \
+        if (a.full) hipLaunchKernelGGL((KERN<__VA_ARGS__, true>), dim3(grid), dim3(NP * 4), 0, s, a); \
+        else hipLaunchKernelGGL((KERN<__VA_ARGS__, false>), dim3(grid), dim3(NP * 4), 0, s, a);      \
+    } while (0)
 
 // grid: work-groups of the launch; loop: a queue launch or a persistent grid
 // (LOOP build), else one work-group per item
@@ -239,18 +256,20 @@ template <int NP>
 static hipError_t launch_gjb(const LadderArgs &a, int occ, int grid, bool loop, hipStream_t s) {
     if constexpr (NP <= 64) {
         if (occ == 3) {
-            if (loop) hipLaunchKernelGGL((k_ladder_gjb_f64_o3<NP, true>), dim3(grid), dim3(NP * 4), 0, s, a);
-            else hipLaunchKernelGGL((k_ladder_gjb_f64_o3<NP, false>), dim3(grid), dim3(NP * 4), 0, s, a);
+            if (loop) DF_LAUNCH_FULL(k_ladder_gjb_f64_o3, NP, true);
+            else DF_LAUNCH_FULL(k_ladder_gjb_f64_o3, NP, false);
             return hipGetLastError();
         }
         if (occ == 4) {
             if (loop) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_ladder_gjb_f64_o4<NP>), dim3(grid), dim3(NP * 4), 0, s, a);
+            DF_LAUNCH_FULL(k_ladder_gjb_f64_o4, NP);
             return hipGetLastError();
         }
     }
-    if (loop) hipLaunchKernelGGL((k_ladder_gjb_f64<NP, true>), dim3(grid), dim3(NP * 4), 0, s, a);
-    else hipLaunchKernelGGL((k_ladder_gjb_f64<NP, false>), dim3(grid), dim3(NP * 4), 0, s, a);
+    if (loop) DF_LAUNCH_FULL(k_ladder_gjb_f64, NP, true);
+    else if (NP == 96 && a.full)   // (the general path needs more registers: one item)
+        hipLaunchKernelGGL((k_ladder_gjb_f64_x2<NP, true>), dim3((grid + 1) / 2), dim3(NP * 8), 0, s, a);
+    else DF_LAUNCH_FULL(k_ladder_gjb_f64, NP, false);
     return hipGetLastError();
 }
 
@@ -260,10 +279,10 @@ static int occupancy_gjb(int occ) {
     int nb = 0;
     hipError_t e;
     if constexpr (NP <= 64) {
-        if (occ == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ladder_gjb_f64_o3<NP, true>, NP * 4, 0);
-        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ladder_gjb_f64<NP, true>, NP * 4, 0);
+        if (occ == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ladder_gjb_f64_o3<NP, true, false>, NP * 4, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ladder_gjb_f64<NP, true, false>, NP * 4, 0);
     } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ladder_gjb_f64<NP, true>, NP * 4, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ladder_gjb_f64<NP, true, false>, NP * 4, 0);
     }
     return e == hipSuccess ? nb : 0;
 }

@@ -59,36 +59,30 @@ template <int NP> struct PlainShared {
     GjShared<float, NP> gj;
 };
 
-// LDS of one item, one allocation per size and class (shared by the FULL and
-// the general item function)
-template <int NP, bool REFINE> struct MixedLds {
-    typename std::conditional<REFINE, MixedShared<NP>, PlainShared<NP>>::type sh;
-    cd ypart[NP];
-    cd tv[NP];
-    int s_flag;
-};
-template <int NP, bool REFINE> __device__ __forceinline__ MixedLds<NP, REFINE> &mixed_lds() {
-    __shared__ MixedLds<NP, REFINE> lds;
-    return lds;
-}
-
 // REFINE = false: the FP32 ladder alone, from FP32 copies of the vertex
 // arrays: D, t and Gamma_nn = sum_l X_nl gamma_ln with X = D^-1 from the FP32
 // sweep, all in FP32.  Relative error of order kappa n eps32, about 1e-6 for
 // certified items.  FULL: n_nu equals the padded size NP (no clamped index,
-// no masked padding).
-template <int NP, bool REFINE, bool FULL>
-__device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
+// no masked padding).  ITEMS = 2 (FP32 ladder alone): two items per
+// work-group, as in the FP64 kernel's two-item build (gjb_item).
+template <int NP, bool REFINE, bool FULL, int ITEMS = 1>
+__device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem, bool dummy = false) {
+    static_assert(ITEMS == 1 || !REFINE, "two items per work-group: FP32 ladder only");
     constexpr int NT = NP / 16;
     typedef MT<float>::v4 f4;
     typedef MT<double>::v4 d4;
-    MixedLds<NP, REFINE> &L = mixed_lds<NP, REFINE>();
-    auto &sh = L.sh;
-    cd *ypart = L.ypart;
-    cd *tv = L.tv;
-    int &s_flag = L.s_flag;
+    typedef typename std::conditional<REFINE, MixedShared<NP>, PlainShared<NP>>::type Shared;
+    __shared__ Shared shv[ITEMS];
+    __shared__ cd ypartv[ITEMS][NP];
+    __shared__ cd tvv[ITEMS][NP];
+    __shared__ int s_flagv[ITEMS];
+    const int half = (ITEMS == 2 && threadIdx.x >= NP * 4) ? 1 : 0;
+    Shared &sh = shv[half];
+    cd *ypart = ypartv[half];
+    cd *tv = tvv[half];
+    int &s_flag = s_flagv[half];
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x - half * (NP * 4);
     const int w = tid >> 6;
     const int l = tid & 63;
     const int lj = l & 15;
@@ -191,13 +185,16 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
     // test) go to the FP64 kernel, which re-certifies them and hands its own
     // uncertified items to the pivoting kernel.
     constexpr double accept = REFINE ? CERT_NEAR_MIXED : CERT_MAX_MIXED;
-    const double cw = gj_certify<float, NP>(Cr, Ci, sh.gj, MIX_CERT_ITERS, accept, tid);
+    const double cw = gj_certify<float, NP>(Cr, Ci, sh.gj, MIX_CERT_ITERS, accept, tid,
+                                            ITEMS == 2 ? &shv[1 - half].gj : nullptr);
+    bool skip = dummy;   // no results of this half are written
     if (!(cw < accept)) {
-        if (tid == 0) {
+        if (tid == 0 && !dummy) {
             if (REFINE && a.near_queue) a.near_queue[atomicAdd(a.near_count, 1)] = gitem;
             else if (a.queue) a.queue[atomicAdd(a.queue_count, 1)] = gitem;
         }
-        return;   // uniform: every thread of the work-group leaves here
+        if constexpr (ITEMS == 1) return;   // uniform: every thread of the work-group leaves here
+        else skip = true;
     }
 
     gj_sweep<float, NP, true>(Cr, Ci, sh.gj, tid);   // look-ahead inversion
@@ -208,9 +205,11 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
         if (l == 0) {
             s_flag = stt;
             const size_t o = (size_t)cm * N + q;
-            if (a.logdet) st(a.logdet, o, ldv);
-            if (a.status) a.status[o] = (int8_t)stt;
-            if (stt != 0 && a.fallback_count) atomicAdd(a.fallback_count, 1);
+            if (!skip) {
+                if (a.logdet) st(a.logdet, o, ldv);
+                if (a.status) a.status[o] = (int8_t)stt;
+                if (stt != 0 && a.fallback_count) atomicAdd(a.fallback_count, 1);
+            }
         }
     }
     __syncthreads();   // also ends every use of sh.gj
@@ -255,18 +254,19 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
             }
         }
         __syncthreads();
-        for (int n = tid; n < n_nu; n += NP * 4) {
-            const cd tt = tv[n];
-            cd wv;
-            if (stt == 0) {
-                const cd y = ypart[n];
-                wv = {y.re - 0.5 * tt.re, y.im - 0.5 * tt.im};
-            } else {
-                const cd gnn = ld(gam, (size_t)n * n_nu + n);
-                wv = {gnn.re + 0.5 * tt.re, gnn.im + 0.5 * tt.im};
+        if (!skip)
+            for (int n = tid; n < n_nu; n += NP * 4) {
+                const cd tt = tv[n];
+                cd wv;
+                if (stt == 0) {
+                    const cd y = ypart[n];
+                    wv = {y.re - 0.5 * tt.re, y.im - 0.5 * tt.im};
+                } else {
+                    const cd gnn = ld(gam, (size_t)n * n_nu + n);
+                    wv = {gnn.re + 0.5 * tt.re, gnn.im + 0.5 * tt.im};
+                }
+                st(a.w, ((size_t)cm * n_nu + n) * N + q, wv);
             }
-            st(a.w, ((size_t)cm * n_nu + n) * N + q, wv);
-        }
     } else {
     // Refinement on this wave's block-row.  The FP32 accumulator layout puts
     // row 4 lg + r of a tile in lane group lg, register r; the FP64 products
@@ -487,46 +487,43 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem) {
 // five.  Builds that cannot hold their work-groups' LDS at that occupancy
 // are not made: the refined kernel's Z0 / E buffer is NP^2 complex floats
 // (72 KB at NP = 96: two work-groups per CU; 128 KB at 128: one).
-template <int NP>
+template <int NP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_ladder_mixed(LadderArgs a0) {
-    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
-    if (item_n_nu(a0, gi) == NP) mixed_item<NP, true, true>(a0, gi);
-    else mixed_item<NP, true, false>(a0, gi);
+    mixed_item<NP, true, FULL>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
 }
-template <int NP>
+template <int NP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(3, 3)))
 void k_ladder_mixed_o3(LadderArgs a0) {
-    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
-    if (item_n_nu(a0, gi) == NP) mixed_item<NP, true, true>(a0, gi);
-    else mixed_item<NP, true, false>(a0, gi);
+    mixed_item<NP, true, FULL>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
 }
-template <int NP>
+template <int NP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ladder_mixed_o4(LadderArgs a0) {
-    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
-    if (item_n_nu(a0, gi) == NP) mixed_item<NP, true, true>(a0, gi);
-    else mixed_item<NP, true, false>(a0, gi);
+    mixed_item<NP, true, FULL>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
 }
-template <int NP>
+template <int NP, bool FULL>
 __global__ __launch_bounds__(NP * 4) void k_ladder_fp32(LadderArgs a0) {
-    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
-    if (item_n_nu(a0, gi) == NP) mixed_item<NP, false, true>(a0, gi);
-    else mixed_item<NP, false, false>(a0, gi);
+    mixed_item<NP, false, FULL>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
 }
-template <int NP>
+template <int NP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ladder_fp32_o4(LadderArgs a0) {
-    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
-    if (item_n_nu(a0, gi) == NP) mixed_item<NP, false, true>(a0, gi);
-    else mixed_item<NP, false, false>(a0, gi);
+    mixed_item<NP, false, FULL>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
 }
-template <int NP>
+template <int NP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(5, 5)))
 void k_ladder_fp32_o5(LadderArgs a0) {
-    const int gi = a0.item0 + xcd_item(blockIdx.x, gridDim.x);
-    if (item_n_nu(a0, gi) == NP) mixed_item<NP, false, true>(a0, gi);
-    else mixed_item<NP, false, false>(a0, gi);
+    mixed_item<NP, false, FULL>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+}
+
+// FP32 ladder, two items per work-group (NP = 96; see k_ladder_gjb_f64_x2)
+template <int NP, bool FULL>
+__global__ __launch_bounds__(NP * 8) void k_ladder_fp32_x2(LadderArgs a0) {
+    const int half = threadIdx.x >= NP * 4 ? 1 : 0;
+    const int k = 2 * xcd_item(blockIdx.x, gridDim.x) + half;
+    const bool dummy = k >= a0.n_items;
+    mixed_item<NP, false, FULL, 2>(a0, a0.item0 + (dummy ? a0.n_items - 1 : k), dummy);
 }
 
 // builds made for each size
@@ -536,6 +533,13 @@ template <int NP> constexpr bool has_mixed_occ(int occ) {
 template <int NP> constexpr bool has_fp32_occ(int occ) {
     return occ == 0 || ((occ == 4 || occ == 5) && NP <= 64);
 }
+
+// the launch of one build with the launch's mask-free choice (LadderArgs::full)
+#define DF_LAUNCH_FULL_M(KERN)                                                          \
+    do {                                                                                \
+        if (a->full) hipLaunchKernelGGL((KERN<NP, true>), dim3(grid), dim3(NP * 4), 0, s, *a); \
+        else hipLaunchKernelGGL((KERN<NP, false>), dim3(grid), dim3(NP * 4), 0, s, *a);        \
+    } while (0)
 
 template <typename K>
 static int occupancy_of(K kern, int threads) {
@@ -550,19 +554,19 @@ static int mixed_build(const LadderArgs *a, int occ, int grid, hipStream_t s, bo
     if (!has_mixed_occ<NP>(occ)) return -1;
     if (occ == 3) {
         if constexpr (NP <= 96) {
-            if (query) return occupancy_of(k_ladder_mixed_o3<NP>, NP * 4);
-            hipLaunchKernelGGL((k_ladder_mixed_o3<NP>), dim3(grid), dim3(NP * 4), 0, s, *a);
+            if (query) return occupancy_of(k_ladder_mixed_o3<NP, false>, NP * 4);
+            DF_LAUNCH_FULL_M(k_ladder_mixed_o3);
             return hipGetLastError() == hipSuccess ? 0 : -1;
         }
     } else if (occ == 4) {
         if constexpr (NP <= 64) {
-            if (query) return occupancy_of(k_ladder_mixed_o4<NP>, NP * 4);
-            hipLaunchKernelGGL((k_ladder_mixed_o4<NP>), dim3(grid), dim3(NP * 4), 0, s, *a);
+            if (query) return occupancy_of(k_ladder_mixed_o4<NP, false>, NP * 4);
+            DF_LAUNCH_FULL_M(k_ladder_mixed_o4);
             return hipGetLastError() == hipSuccess ? 0 : -1;
         }
     } else {
-        if (query) return occupancy_of(k_ladder_mixed<NP>, NP * 4);
-        hipLaunchKernelGGL((k_ladder_mixed<NP>), dim3(grid), dim3(NP * 4), 0, s, *a);
+        if (query) return occupancy_of(k_ladder_mixed<NP, false>, NP * 4);
+        DF_LAUNCH_FULL_M(k_ladder_mixed);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     return -1;
@@ -574,18 +578,20 @@ static int fp32_build(const LadderArgs *a, int occ, int grid, hipStream_t s, boo
     if (occ == 4 || occ == 5) {
         if constexpr (NP <= 64) {
             if (occ == 4) {
-                if (query) return occupancy_of(k_ladder_fp32_o4<NP>, NP * 4);
-                hipLaunchKernelGGL((k_ladder_fp32_o4<NP>), dim3(grid), dim3(NP * 4), 0, s, *a);
+                if (query) return occupancy_of(k_ladder_fp32_o4<NP, false>, NP * 4);
+                DF_LAUNCH_FULL_M(k_ladder_fp32_o4);
             } else {
-                if (query) return occupancy_of(k_ladder_fp32_o5<NP>, NP * 4);
-                hipLaunchKernelGGL((k_ladder_fp32_o5<NP>), dim3(grid), dim3(NP * 4), 0, s, *a);
+                if (query) return occupancy_of(k_ladder_fp32_o5<NP, false>, NP * 4);
+                DF_LAUNCH_FULL_M(k_ladder_fp32_o5);
             }
             return hipGetLastError() == hipSuccess ? 0 : -1;
         }
         return -1;
     }
-    if (query) return occupancy_of(k_ladder_fp32<NP>, NP * 4);
-    hipLaunchKernelGGL((k_ladder_fp32<NP>), dim3(grid), dim3(NP * 4), 0, s, *a);
+    if (query) return occupancy_of(k_ladder_fp32<NP, false>, NP * 4);
+    if (NP == 96 && grid == a->n_items && a->full && !a->in_queue && !a->claim)
+        hipLaunchKernelGGL((k_ladder_fp32_x2<NP, true>), dim3((grid + 1) / 2), dim3(NP * 8), 0, s, *a);
+    else DF_LAUNCH_FULL_M(k_ladder_fp32);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
