@@ -222,21 +222,25 @@ def converge_each(B, problems, insts, ws, prec, stream, graph, sigma0=None, acce
     return out
 
 
-KERNEL_SYMBOL = {"gjb": "k_ladder_gjb_f64<{np}, false>", "gjb_o3": "k_ladder_gjb_f64_o3<{np}, false>",
-                 "gjb_o4": "k_ladder_gjb_f64_o4<{np}>",
-                 "vector": "k_ladder_fp64<{np},...>", "mfma": "k_ladder_mfma_f64<{np}>",
-                 "mixed": "k_ladder_mixed<{np}>", "mixed_o3": "k_ladder_mixed_o3<{np}>",
-                 "mixed_o4": "k_ladder_mixed_o4<{np}>",
-                 "fp32": "k_ladder_fp32<{np}>", "fp32_o4": "k_ladder_fp32_o4<{np}>",
-                 "fp32_o5": "k_ladder_fp32_o5<{np}>"}
-
-
-def kernel_symbol(variant: str, np_: int) -> str:
-    """Kernel of a variant name; persistent grids ("@p1", "@p2") run the
-    item-loop build of the same kernel."""
+def kernel_symbol(variant: str, np_: int, full: bool = True) -> str:
+    """Kernel of a variant name at padded size np_; full: the launch's instances
+    all have n_nu = np_ (the mask-free builds).  Persistent grids ("@p1", "@p2")
+    run the item-loop build of the same kernel; at np_ = 96 the one-item-per-slot
+    launches of gjb and fp32 hold two items per work-group."""
     base, _, persist = variant.partition("@")
-    sym = KERNEL_SYMBOL[base].format(np=np_)
-    return sym.replace(", false>", ", true>") if persist else sym
+    f = "true" if full else "false"
+    loop = "true" if persist else "false"
+    if base == "gjb" and np_ == 96 and full and not persist:
+        return "k_ladder_gjb_f64_xk<96, true, 2>"
+    if base == "fp32" and np_ == 96 and full:
+        return "k_ladder_fp32_x2<96, true>"
+    table = {"gjb": f"k_ladder_gjb_f64<{np_}, {loop}, {f}>",
+             "gjb_o3": f"k_ladder_gjb_f64_o3<{np_}, {loop}, {f}>",
+             "gjb_o4": f"k_ladder_gjb_f64_o4<{np_}, {f}>",
+             "vector": f"k_ladder_fp64<{np_},...>", "mfma": f"k_ladder_mfma_f64<{np_}>"}
+    for k in ("mixed", "mixed_o3", "mixed_o4", "fp32", "fp32_o4", "fp32_o5"):
+        table[k] = f"k_ladder_{k}<{np_}, {f}>"
+    return table[base]
 
 
 def roofline_of(prec, B, n_om, N, n_nu, lad_ms, n_inst=1):

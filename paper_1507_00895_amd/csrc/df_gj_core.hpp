@@ -253,15 +253,17 @@ __device__ __forceinline__ double wave_sum(double x) {
 // within n * 2^-24 relative of the exact ones, and the bound is inflated by
 // (1 + 1e-5) to stay an upper bound.  Contains barriers: every thread must call.
 //
-// other: the state of a second item in the same work-group (two items per
-// work-group), or null.  With two items the loop stops only when both bounds
-// pass, so that both items take the same barriers; the bound of an item that
-// passed earlier keeps shrinking (the quotient of a power step never rises).
+// peers, n_peers: the states of all items of the work-group when it holds
+// several (one per slot of waves), else null.  Then the loop stops only when
+// every item's bound passes, so that all items take the same barriers; the
+// bound of an item that passed earlier keeps shrinking (the quotient of a
+// power step never rises).
 template <typename T, int NP>
 __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP / 16],
                                              const typename MT<T>::v4 (&Ci)[NP / 16],
                                              GjShared<T, NP> &sh, int iters, double accept,
-                                             int tid, const GjShared<T, NP> *other = nullptr) {
+                                             int tid, const GjShared<T, NP> *peers = nullptr,
+                                             int n_peers = 0) {
     constexpr int NT = NP / 16;
     const int w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
     // step 0 starts from v = 1 without reading it (no barrier before it)
@@ -306,9 +308,9 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
         if (bound) {
             double c = 0.0, co = 0.0;
             for (int x = 0; x < NT; ++x) c = sh.wmax[it & 1][x] > c ? sh.wmax[it & 1][x] : c;
-            if (other)
+            for (int k = 0; k < n_peers; ++k)
                 for (int x = 0; x < NT; ++x)
-                    co = other->wmax[it & 1][x] > co ? other->wmax[it & 1][x] : co;
+                    co = peers[k].wmax[it & 1][x] > co ? peers[k].wmax[it & 1][x] : co;
             // rcpf is within 1 ulp; the factor covers it and the sums' rounding
             cw = c * (1.0 + 1e-5);
             // uniform: every thread of the work-group read the same wmax

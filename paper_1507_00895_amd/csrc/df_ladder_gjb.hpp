@@ -21,12 +21,12 @@ constexpr double CERT_MAX_F64 = 0.999;
 // LOOP: the work-group may run several items in turn (a queue or a
 // persistent grid, for_each_item).  FULL: n_nu equals the padded size NP, so
 // no index is clamped and no padding is masked (measured 2-3 % faster than
-// the general path on the same items).  ITEMS = 2: the work-group holds two
-// items, one per half (k_ladder_gjb_f64_x2); both halves take every barrier,
-// so an uncertified item is not left early but carried through with its
-// results discarded, and `dummy` marks a half without an item of its own
-// (odd item counts), which computes a copy of the last item and writes
-// nothing.
+// the general path on the same items).  ITEMS > 1: the work-group holds
+// several items, one per slot of NP / 16 waves (k_ladder_gjb_f64_xk); all
+// slots take every barrier, so an uncertified item is not left early but
+// carried through with its results discarded, and `dummy` marks a slot
+// without an item of its own (the last work-group of the launch), which
+// computes a copy of the last item and writes nothing.
 template <int NP, bool LOOP, bool FULL, int ITEMS = 1>
 __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = false) {
     constexpr int NT = NP / 16;
@@ -35,15 +35,15 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = 
     __shared__ cd yvv[ITEMS][NP];
     __shared__ cd tvv[ITEMS][NP];
     __shared__ int s_flagv[ITEMS];
-    const int half = (ITEMS == 2 && threadIdx.x >= NP * 4) ? 1 : 0;
-    GjShared<double, NP> &sh = shv[half];
-    cd *yv = yvv[half];
-    cd *tv = tvv[half];
-    int &s_flag = s_flagv[half];
+    const int slot = ITEMS > 1 ? (int)threadIdx.x / (NP * 4) : 0;
+    GjShared<double, NP> &sh = shv[slot];
+    cd *yv = yvv[slot];
+    cd *tv = tvv[slot];
+    int &s_flag = s_flagv[slot];
 
     // in an item loop, an opaque copy of the thread index per item (see
     // df_gj_core.hpp)
-    int tid = threadIdx.x - half * (NP * 4);
+    int tid = threadIdx.x - slot * (NP * 4);
     if constexpr (LOOP) asm volatile("" : "+v"(tid));
     const int w = tid >> 6;
     const int l = tid & 63;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = 
     }
 
     const double cw = gj_certify<double, NP>(Cr, Ci, sh, CERT_ITERS, CERT_MAX_F64, tid,
-                                             ITEMS == 2 ? &shv[1 - half] : nullptr);
+                                             ITEMS > 1 ? shv : nullptr, ITEMS > 1 ? ITEMS : 0);
     bool skip = dummy;   // no results of this half are written
     if (!(cw < CERT_MAX_F64)) {
         if (tid == 0 && a.queue && !dummy) a.queue[atomicAdd(a.queue_count, 1)] = gitem;
@@ -230,18 +230,22 @@ void k_ladder_gjb_f64_o4(LadderArgs a0) {
     DF_GJB_BODY(NP, false, FULL)
 }
 
-// Two items per work-group (NP = 96): an item is six waves, and with six-wave
-// work-groups a CU held one work-group even where the registers allowed
-// three waves per SIMD (1.5 waves per SIMD measured); a twelve-wave
-// work-group of two items fills three per SIMD.  Items 2 p and 2 p + 1 of
-// the launch, p the XCD-mapped work-group index.
-template <int NP, bool FULL>
-__global__ __launch_bounds__(NP * 8) void k_ladder_gjb_f64_x2(LadderArgs a0) {
-    const int half = threadIdx.x >= NP * 4 ? 1 : 0;
-    const int k = 2 * xcd_item(blockIdx.x, gridDim.x) + half;
+// K items per work-group: an item is NP / 16 waves, and with six-wave
+// work-groups (NP = 96) a CU held one work-group even where the registers
+// allowed three waves per SIMD (1.5 waves per SIMD measured); a twelve-wave
+// work-group of two items fills three per SIMD.  Items K p .. K p + K - 1
+// of the launch, p the XCD-mapped work-group index.
+template <int NP, bool FULL, int K>
+__global__ __launch_bounds__(NP * 4 * K) void k_ladder_gjb_f64_xk(LadderArgs a0) {
+    const int slot = (int)threadIdx.x / (NP * 4);
+    const int k = K * xcd_item(blockIdx.x, gridDim.x) + slot;
     const bool dummy = k >= a0.n_items;
-    gjb_item<NP, false, FULL, 2>(a0, a0.item0 + (dummy ? a0.n_items - 1 : k), dummy);
+    gjb_item<NP, false, FULL, K>(a0, a0.item0 + (dummy ? a0.n_items - 1 : k), dummy);
 }
+// items per work-group of the FP64 build with the compiler's register budget
+// (mask-free launches only).  At NP = 32 and 48 four items per work-group
+// measured 7-20 % slower than one: only the six-wave items gain.
+template <int NP> constexpr int gjb_items_per_group() { return NP == 96 ? 2 : 1; }
 
 // the launch of one build with the launch's FULL choice
 #define DF_LAUNCH_FULL(KERN, ...)                                                       \
@@ -267,9 +271,14 @@ static hipError_t launch_gjb(const LadderArgs &a, int occ, int grid, bool loop, 
         }
     }
     if (loop) DF_LAUNCH_FULL(k_ladder_gjb_f64, NP, true);
-    else if (NP == 96 && a.full)   // (the general path needs more registers: one item)
-        hipLaunchKernelGGL((k_ladder_gjb_f64_x2<NP, true>), dim3((grid + 1) / 2), dim3(NP * 8), 0, s, a);
-    else DF_LAUNCH_FULL(k_ladder_gjb_f64, NP, false);
+    else if constexpr (gjb_items_per_group<NP>() > 1) {
+        constexpr int K = gjb_items_per_group<NP>();
+        // (the general path needs more registers: one item per work-group)
+        if (a.full)
+            hipLaunchKernelGGL((k_ladder_gjb_f64_xk<NP, true, K>), dim3((grid + K - 1) / K),
+                               dim3(NP * 4 * K), 0, s, a);
+        else DF_LAUNCH_FULL(k_ladder_gjb_f64, NP, false);
+    } else DF_LAUNCH_FULL(k_ladder_gjb_f64, NP, false);
     return hipGetLastError();
 }
 

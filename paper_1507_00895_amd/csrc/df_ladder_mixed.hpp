@@ -186,7 +186,8 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem, bool dummy 
     // uncertified items to the pivoting kernel.
     constexpr double accept = REFINE ? CERT_NEAR_MIXED : CERT_MAX_MIXED;
     const double cw = gj_certify<float, NP>(Cr, Ci, sh.gj, MIX_CERT_ITERS, accept, tid,
-                                            ITEMS == 2 ? &shv[1 - half].gj : nullptr);
+                                            ITEMS == 2 ? &shv[ITEMS - 1 - half].gj : nullptr,
+                                            ITEMS == 2 ? 1 : 0);
     bool skip = dummy;   // no results of this half are written
     if (!(cw < accept)) {
         if (tid == 0 && !dummy) {

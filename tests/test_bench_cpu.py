@@ -58,7 +58,10 @@ def test_roofline_arithmetic():
     assert r["algorithmic_flops_per_launch"] == flops
     assert r["achieved"] == pytest.approx(flops / 3e-3 / 1e12)
     assert r["frac"] == pytest.approx(r["achieved"] / 78.6)
-    assert r["kernel"] == "k_ladder_gjb_f64_o4<64>"
+    assert r["kernel"] == "k_ladder_gjb_f64_o4<64, true>"
+    assert bench.kernel_symbol("gjb@p1", 128) == "k_ladder_gjb_f64<128, true, true>"
+    assert bench.kernel_symbol("gjb", 96) == "k_ladder_gjb_f64_xk<96, true, 2>"
+    assert bench.kernel_symbol("mixed", 96) == "k_ladder_mixed<96, true>"
     r = bench.roofline_of(2, _FakeLib("fp32_o4"), n_om, N, n_nu, ms)
     assert r["peak"] == 157.3 and r["algorithmic_flops_per_launch"] == flops
     # refined solve: 16 n^3 in FP32 and 8 n^3 in FP64, each at its own peak
