@@ -373,6 +373,15 @@ __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename 
     }
 }
 
+// Wave priority around a tile inversion, FP32 sweeps only: the inverting
+// wave is the item's critical path, and raising its issue priority over the
+// other waves of the SIMD (other items' updates) measured 3-5 % faster for
+// the FP32 and refined builds; in the FP64 builds it measured slower (and
+// the four-wave build spilled more around the priority changes).
+template <typename T, bool HIGH> __device__ __forceinline__ void inversion_priority() {
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(HIGH ? 2 : 0);
+}
+
 // Scheduling pattern for the current scheduling region: NM times one matrix
 // instruction followed by up to NO vector-ALU, scalar-ALU, LDS or
 // transcendental instructions, so that a wave's matrix products issue between
@@ -543,7 +552,11 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
     typedef cplx<T> ct;
     typedef typename MT<T>::v4 v4;
     const int w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
-    if (w == 0) gj_tile_invert<T>(Cr[0], Ci[0], sh.pivv, tid);
+    if (w == 0) {
+        inversion_priority<T, true>();
+        gj_tile_invert<T>(Cr[0], Ci[0], sh.pivv, tid);
+        inversion_priority<T, false>();
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (w == t) {
@@ -624,7 +637,9 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 if (ahead) {
                     update(1, 2);
                     __builtin_amdgcn_sched_barrier(0);
+                    inversion_priority<T, true>();
                     gj_tile_invert<T>(Cr[1], Ci[1], sh.pivv + 16 * (t + 1), tid);
+                    inversion_priority<T, false>();
                     update(2, NT);
                     interleave_mfma<12 * (NT - 2), 20>();
                 } else {
@@ -677,7 +692,9 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 if (ahead) {
                     update(1, 2);
                     __builtin_amdgcn_sched_barrier(0);
+                    inversion_priority<T, true>();
                     gj_tile_invert<T>(Cr[1], Ci[1], sh.pivv + 16 * (t + 1), tid);
+                    inversion_priority<T, false>();
                     update(2, NT);
                     interleave_mfma<16 * (NT - 2), 28>();
                 } else {
