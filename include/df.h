@@ -140,6 +140,16 @@ typedef struct {
  *               that is point-group invariant with Sigma~(-nu) = Sigma~(nu)* - as
  *               those of the hypercubic Hubbard model are; the iteration keeps
  *               them.  Results then equal those of symmetry 0 to rounding.
+ *   graph_unroll  df_iterate with use_graph, accel 0 and prec DF_FP64,
+ *               DF_FP32_REFINE or DF_FP32: iterations per captured graph, 0..64
+ *               (0 and 1: one).  The convergence measure and the fallback
+ *               counts are then read once per graph launch, after its last
+ *               iteration: an instance may run up to graph_unroll - 1
+ *               iterations past the one whose diff fell below tol (iters_out
+ *               counts the iterations run), and the host waits once per
+ *               graph_unroll iterations instead of once per iteration.  With
+ *               tol <= 0 the results are those of graph_unroll 0.  DF_ADAPTIVE
+ *               and accel > 0 take a host step every iteration and ignore it.
  */
 typedef struct {
     int32_t prec;
@@ -150,6 +160,7 @@ typedef struct {
     int32_t use_graph;
     int32_t accel;
     int32_t symmetry;
+    int32_t graph_unroll;
 } df_opts_t;
 
 /* Workspace bytes needed by any entry point for these instances and options. */

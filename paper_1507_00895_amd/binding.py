@@ -55,7 +55,7 @@ class DfOpts(ctypes.Structure):
     _fields_ = [
         ("prec", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("mix", ctypes.c_double),
         ("tol", ctypes.c_double), ("switch_tol", ctypes.c_double), ("use_graph", ctypes.c_int32),
-        ("accel", ctypes.c_int32), ("symmetry", ctypes.c_int32),
+        ("accel", ctypes.c_int32), ("symmetry", ctypes.c_int32), ("graph_unroll", ctypes.c_int32),
     ]
 
 
@@ -198,9 +198,9 @@ def _arr(insts: Sequence[Instance]):
 
 
 def _opts(prec=DF_FP64, mix=0.5, tol=0.0, max_iter=10, use_graph=0, switch_tol=0.0,
-          accel=0, symmetry=0) -> DfOpts:
+          accel=0, symmetry=0, graph_unroll=0) -> DfOpts:
     return DfOpts(int(prec), int(max_iter), float(mix), float(tol), float(switch_tol),
-                  int(use_graph), int(accel), int(symmetry))
+                  int(use_graph), int(accel), int(symmetry), int(graph_unroll))
 
 
 def make_opts(**kw) -> DfOpts:

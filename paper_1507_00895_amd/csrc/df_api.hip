@@ -460,11 +460,14 @@ int stage_reduce_mix(const Shape &s, const double *part, double *sigma_calc, dou
 bool ladder_prec(int prec) { return prec == DF_FP64 || prec == DF_FP32_REFINE || prec == DF_FP32; }
 
 // need_loop: df_iterate's fields are checked too; adaptive: DF_ADAPTIVE allowed
+constexpr int kMaxGraphUnroll = 64;
+
 int check_opts(const df_opts_t *o, bool need_loop, bool adaptive) {
     if (!o) return need_loop ? DF_E_INVAL : DF_OK;
     if (!ladder_prec(o->prec) && !(adaptive && o->prec == DF_ADAPTIVE)) return DF_E_INVAL;
     if (o->accel < 0 || o->accel > kAccMaxSlots - 1 || !isfinite(o->switch_tol)) return DF_E_INVAL;
     if (o->symmetry != 0 && o->symmetry != 1) return DF_E_INVAL;
+    if (o->graph_unroll < 0 || o->graph_unroll > kMaxGraphUnroll) return DF_E_INVAL;
     if (need_loop) {
         if (!(o->mix > 0.0 && o->mix <= 1.0)) return DF_E_INVAL;
         if (o->max_iter < 1) return DF_E_INVAL;
@@ -1024,6 +1027,10 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
     if (rc != DF_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     const bool graph = opts->use_graph != 0 && st != nullptr;
+    // iterations per captured graph: the host step of Anderson acceleration
+    // and of the adaptive precision switch needs every iteration's measure
+    const int unroll = (graph && slots == 0 && opts->prec != DF_ADAPTIVE && opts->graph_unroll > 1)
+                           ? opts->graph_unroll : 1;
 
     for (int i = 0; i < n_inst; ++i) {
         rc = stage_gamma_prep(inst[i], P.shape[i], ws, P.base[i], P.lay[i], st);
@@ -1065,7 +1072,9 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
                 hipGraph_t g = nullptr;
                 if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
                     return DF_E_HIP;
-                rc = queue_fused_iteration(inst, P, F, *opts, ws, st);
+                rc = DF_OK;
+                for (int u = 0; u < unroll && rc == DF_OK; ++u)
+                    rc = queue_fused_iteration(inst, P, F, *opts, ws, st);
                 const hipError_t e = hipStreamEndCapture(st, &g);
                 if (rc != DF_OK || e != hipSuccess) {
                     if (g) (void)hipGraphDestroy(g);
@@ -1077,16 +1086,25 @@ int df_iterate(const df_inst_t *inst, int32_t n_inst, const df_opts_t *opts, int
             }
             rebuild = false;
         }
-        if (graph) {
+        if (graph && opts->max_iter - it >= unroll) {
             if (hipGraphLaunch(exec, st) != hipSuccess) {
                 cleanup();
                 return DF_E_HIP;
             }
+            it += unroll;
         } else {
-            rc = queue_fused_iteration(inst, P, F, *opts, ws, st);
-            if (rc != DF_OK) return rc;
+            // without a graph, or the iterations left are fewer than one
+            // graph's: queued one by one
+            const int n = graph ? opts->max_iter - it : 1;
+            for (int u = 0; u < n; ++u) {
+                rc = queue_fused_iteration(inst, P, F, *opts, ws, st);
+                if (rc != DF_OK) {
+                    cleanup();
+                    return rc;
+                }
+            }
+            it += n;
         }
-        ++it;
         if (slots > 0) {
             // record x_k, r_k and their dots; weights on the host; the step
             for (int i : act) {

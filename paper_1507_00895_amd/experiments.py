@@ -15,7 +15,7 @@ g_inf from a fit g_x = g_inf + a x^-p over the five largest points of the
 sweep (the paper extrapolates N_x -> infinity, eq. deltag, without saying
 how; a power law is what its Figs. 1 and 2 show).
 
-    python -m paper_1507_00895_amd.experiments --sweep om|nu|k|all [--repeat R]
+    python -m paper_1507_00895_amd.experiments --sweep om|nu|k|all [--repeat R] [--graph-unroll U]
 
 prints one JSON object per sweep.  Every step runs in libdf's kernels.
 """
@@ -37,13 +37,15 @@ SWEEPS = {
 }
 
 
-def converge_point(B, inputs, D, nk, n_nu, n_om, repeat=3, tol=1e-10):
+def converge_point(B, inputs, D, nk, n_nu, n_om, repeat=3, tol=1e-10, unroll=4):
     """Converge one point; returns (best wall seconds, g = G~(i pi/beta, k=0), iterations,
-    whether tol was reached)."""
+    whether tol was reached).  unroll: iterations per captured graph (the
+    convergence measure is read once per graph launch, so up to unroll - 1
+    iterations run past convergence; the per-iteration host wait goes)."""
     import torch
     p = inputs.atomic_limit_problem(D, nk, n_nu, n_om, BETA, U, T_HOP)
     x = B.make_instance(p)
-    opts = B.make_opts(mix=0.5, tol=tol, max_iter=500, use_graph=1)
+    opts = B.make_opts(mix=0.5, tol=tol, max_iter=500, use_graph=1, graph_unroll=unroll)
     ws = B.workspace([x], opts)
     stream = torch.cuda.Stream()
     best, it, code = None, 0, 0
@@ -90,7 +92,7 @@ def extrapolate(xs, gs, tail=5):
     return complex(c[0]), float(best)
 
 
-def run_sweep(name, repeat=3):
+def run_sweep(name, repeat=3, unroll=4):
     from paper_1507_00895_amd import binding as B
     from paper_1507_00895_amd import inputs
     cfg = SWEEPS[name]
@@ -98,7 +100,8 @@ def run_sweep(name, repeat=3):
     for v in cfg["values"]:
         kw = dict(nk=cfg["nk"], n_nu=cfg["n_nu"], n_om=cfg["n_om"])
         kw[cfg["param"]] = v
-        sec, g, it, ok = converge_point(B, inputs, 2, kw["nk"], kw["n_nu"], kw["n_om"], repeat)
+        sec, g, it, ok = converge_point(B, inputs, 2, kw["nk"], kw["n_nu"], kw["n_om"], repeat,
+                                        unroll=unroll)
         rows.append({cfg["param"]: v, "seconds": sec, "iterations": it, "converged": ok,
                      "g": [g.real, g.imag]})
         print(f"[experiments] {name} {cfg['param']}={v}: {sec * 1e3:.2f} ms, {it} iterations",
@@ -109,7 +112,8 @@ def run_sweep(name, repeat=3):
     for r, g in zip(rows, gs):
         r["delta_g"] = abs(g - ginf) / abs(ginf)
     return {"sweep": name, "fixed": {k: cfg[k] for k in ("n_nu", "nk", "n_om") if cfg[k] is not None},
-            "U": U, "beta": BETA, "t": T_HOP, "tol": 1e-10, "g_inf": [ginf.real, ginf.imag],
+            "U": U, "beta": BETA, "t": T_HOP, "tol": 1e-10, "graph_unroll": unroll,
+            "g_inf": [ginf.real, ginf.imag],
             "fit_power": power, "points": rows}
 
 
@@ -117,12 +121,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sweep", choices=["om", "nu", "k", "all"], default="all")
     ap.add_argument("--repeat", type=int, default=3)
+    ap.add_argument("--graph-unroll", type=int, default=4,
+                    help="iterations per captured graph (df_opts_t.graph_unroll)")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the sweeps run on the GPU path"
     names = ["om", "nu", "k"] if args.sweep == "all" else [args.sweep]
     for n in names:
-        print(json.dumps(run_sweep(n, args.repeat)), flush=True)
+        print(json.dumps(run_sweep(n, args.repeat, args.graph_unroll)), flush=True)
 
 
 if __name__ == "__main__":

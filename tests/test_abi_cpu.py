@@ -48,10 +48,11 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "df.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(df_inst_t), offsetof(df_inst_t, beta),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(df_inst_t), offsetof(df_inst_t, beta),
          offsetof(df_inst_t, g), offsetof(df_inst_t, status), sizeof(df_opts_t),
          offsetof(df_opts_t, max_iter), offsetof(df_opts_t, tol), offsetof(df_opts_t, switch_tol),
-         offsetof(df_opts_t, accel), offsetof(df_opts_t, symmetry));
+         offsetof(df_opts_t, accel), offsetof(df_opts_t, symmetry),
+         offsetof(df_opts_t, graph_unroll));
   return 0;
 }
 ''')
@@ -62,7 +63,7 @@ int main(void) {
     assert vals == [ctypes.sizeof(B.DfInst), B.DfInst.beta.offset, B.DfInst.g.offset,
                     B.DfInst.status.offset, ctypes.sizeof(B.DfOpts), B.DfOpts.max_iter.offset,
                     B.DfOpts.tol.offset, B.DfOpts.switch_tol.offset, B.DfOpts.accel.offset,
-                    B.DfOpts.symmetry.offset]
+                    B.DfOpts.symmetry.offset, B.DfOpts.graph_unroll.offset]
 
 
 def _inst(**kw):

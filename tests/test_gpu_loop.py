@@ -120,3 +120,38 @@ def test_paper_sweep_point_converged_against_oracle(B):
     G = O.dual_gf(O.dual_gf0(p.g, p.delta, p.eps), r.sigma)
     g_gpu = host(inst.gd)[n0, 0]
     assert abs(g_gpu - G[n0, 0]) <= 1e-9 * abs(G[n0, 0])
+
+
+@pytest.mark.parametrize("unroll", [3, 4])
+def test_graph_unroll_runs_the_same_iterations(B, unroll):
+    """graph_unroll captures several iterations per graph and reads the
+    convergence measure once per launch.  With tol = 0 the iterations are
+    those of one iteration per graph (10 = 3 + 3 + 3 + 1 or 4 + 4 + 2, the
+    remainder queued one by one): Sigma~ bit-identical.  With tol > 0 the
+    loop stops at the end of a graph launch whose last diff is below tol, at
+    most unroll - 1 iterations after the plain loop would, and stays within
+    the plain loop's tolerance of the oracle's fixed point."""
+    import torch
+    p = I.atomic_limit_problem(2, 8, 16, 3, 10.0, 2.0, 0.1)
+    s = torch.cuda.Stream()
+
+    def run(**kw):
+        inst = B.make_instance(p)
+        ws = B.workspace([inst])
+        torch.cuda.synchronize()
+        code, iters, d = B.df_iterate([inst], ws, B.make_opts(mix=0.5, use_graph=1, **kw),
+                                      stream=s.cuda_stream,
+                                      allow=(B.DF_OK, B.DF_W_FALLBACK, B.DF_E_NOT_CONVERGED))
+        s.synchronize()
+        return code, iters, d, host(inst.sigma)
+
+    _, it0, _, s0 = run(tol=0.0, max_iter=10)
+    _, it1, _, s1 = run(tol=0.0, max_iter=10, graph_unroll=unroll)
+    assert it0 == it1 == 10
+    assert np.array_equal(s0, s1)
+
+    c0, n0, d0, t0 = run(tol=1e-11, max_iter=200)
+    c1, n1, d1, t1 = run(tol=1e-11, max_iter=200, graph_unroll=unroll)
+    assert c0 == c1 == B.DF_OK and d0[0] < 1e-11 and d1[0] < 1e-11
+    assert n0 <= n1 <= n0 + unroll - 1 and n1 % unroll == 0
+    assert rel(t1, t0) <= 1e-10
