@@ -198,6 +198,17 @@ __device__ __forceinline__ double wave_max_pos(double x) {
 // ---------------------------------------------------------------- shared state
 // The inverted diagonal tile of step t is published in Xw[t]: the wave that
 // inverts it has no layout exchange of its own at that step.
+// Store a complex value to LDS as two separate stores of its parts: a
+// 16-byte (FP64) or 8-byte (FP32) store of the pair needs the parts in
+// adjacent registers, and the parts of a tile element sit in two different
+// accumulator tiles, so each such store cost register copies (two per value
+// in FP64).  The volatile store (to the LDS address space: d is in LDS)
+// keeps the two from being merged back.
+template <typename T> __device__ __forceinline__ void put_split(cplx<T> &d, T re, T im) {
+    d.re = re;
+    *(volatile __attribute__((address_space(3))) T *)(&d.im) = im;
+}
+
 template <typename T, int NP> struct GjShared {
     static constexpr int NT = NP / 16;
     cplx<T> Rb[16][NP];          // old block-row of the current tile column
@@ -416,16 +427,16 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
                 const int c = (p + t) % NT;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    sh.Rb[MT<T>::row(lg, r)][16 * c + lj] = ct{Cr[p][r], Ci[p][r]};
+                    put_split<T>(sh.Rb[MT<T>::row(lg, r)][16 * c + lj], Cr[p][r], Ci[p][r]);
             }
             v4 &Xr = Cr[0];
             v4 &Xi = Ci[0];
             gj_tile_invert<T>(Xr, Xi, sh.pivv + 16 * t, tid);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sh.Xw[t][MT<T>::row(lg, r)][lj] = ct{Xr[r], Xi[r]};
+            for (int r = 0; r < 4; ++r) put_split<T>(sh.Xw[t][MT<T>::row(lg, r)][lj], Xr[r], Xi[r]);
         } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Cr[0][r], Ci[0][r]};
+            for (int r = 0; r < 4; ++r) put_split<T>(sh.Xw[w][MT<T>::row(lg, r)][lj], Cr[0][r], Ci[0][r]);
         }
         __syncthreads();
 
@@ -456,7 +467,7 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
                 Ci[0] = Gi;
                 wave_sync_lds();
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Gr[r], Gi[r]};
+                for (int r = 0; r < 4; ++r) put_split<T>(sh.Xw[w][MT<T>::row(lg, r)][lj], Gr[r], Gi[r]);
                 wave_sync_lds();
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
@@ -504,7 +515,7 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
                 Ci[0] = Gi;
                 wave_sync_lds();
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Gr[r], Gi[r]};
+                for (int r = 0; r < 4; ++r) put_split<T>(sh.Xw[w][MT<T>::row(lg, r)][lj], Gr[r], Gi[r]);
                 wave_sync_lds();
             }
             // FP64: the A operand comes from LDS one k-slice at a time, used
@@ -565,12 +576,12 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 const int c = (p + t) % NT;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    sh.Rb[MT<T>::row(lg, r)][16 * c + lj] = ct{Cr[p][r], Ci[p][r]};
+                    put_split<T>(sh.Rb[MT<T>::row(lg, r)][16 * c + lj], Cr[p][r], Ci[p][r]);
             }
         }
         // every wave publishes its tile of column t: the inverse for w = t
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Cr[0][r], Ci[0][r]};
+        for (int r = 0; r < 4; ++r) put_split<T>(sh.Xw[w][MT<T>::row(lg, r)][lj], Cr[0][r], Ci[0][r]);
         __syncthreads();
         // wave t + 1 inverts its next diagonal tile inside this step
         const bool ahead = (t + 1 < NT) && (w == t + 1);
@@ -602,7 +613,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 Ci[0] = Gi;
                 wave_sync_lds();
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Gr[r], Gi[r]};
+                for (int r = 0; r < 4; ++r) put_split<T>(sh.Xw[w][MT<T>::row(lg, r)][lj], Gr[r], Gi[r]);
                 wave_sync_lds();
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) {
@@ -666,7 +677,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                 Ci[0] = Gi;
                 wave_sync_lds();
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sh.Xw[w][MT<T>::row(lg, r)][lj] = ct{Gr[r], Gi[r]};
+                for (int r = 0; r < 4; ++r) put_split<T>(sh.Xw[w][MT<T>::row(lg, r)][lj], Gr[r], Gi[r]);
                 wave_sync_lds();
             }
             // FP64: the A operand comes from LDS one k-slice at a time, used
@@ -724,24 +735,45 @@ __device__ __forceinline__ void gj_sweep(typename MT<T>::v4 (&Cr)[NP / 16],
     else gj_sweep_plain<T, NP>(Cr, Ci, sh, tid);
 }
 
-// log det from the scalar pivots (no row exchanges), by wave 0; returns the
-// status code (0 inside, 1 outside, 2 non-finite) to lane 0 of wave 0.
+// log det from the scalar pivots (no row exchanges), by one wave.  det D is
+// the product of the pivots: each lane multiplies its pivots (two at NP > 64)
+// and scales the product by a power of two to max(|re|, |im|) in [0.5, 1)
+// (so |p| in [0.5, sqrt 2): 64 such factors neither overflow nor underflow),
+// the lanes' factors are multiplied by a tree (DPP within each 16-lane row,
+// then the four row products) and their exponents summed; one complex
+// logarithm follows, log |det| = log |P| + E ln 2 with ln 2 split in a high
+// part exact in products with small integers and a low part (Cody and
+// Waite), arg det = arg P.  The status is decided by the sign of Re det =
+// 2^E Re P: 0 inside (Re det > 0), 1 outside, 2 non-finite.  Uniform result.
+template <int CTRL> __device__ __forceinline__ cd dpp_c(cd v) {
+    return {dpp_d<CTRL>(v.re), dpp_d<CTRL>(v.im)};
+}
+__device__ __forceinline__ cd readlane_c(cd v, int lane) {
+    return {readlane_v(v.re, lane), readlane_v(v.im, lane)};
+}
 template <int NP>
 __device__ __forceinline__ int gj_logdet(const cd *pivv, cd *out_logdet, int tid) {
     const int l = tid & 63;
-    double lre = 0.0, lim = 0.0;
-    for (int k = l; k < NP; k += 64) {
-        const cd pv = pivv[k];
-        lre += log(hypot(pv.re, pv.im));
-        lim += atan2(pv.im, pv.re);
+    cd p = (l < NP) ? pivv[l] : cd{1.0, 0.0};
+    if constexpr (NP > 64) {
+        if (l + 64 < NP) p = p * pivv[l + 64];
     }
-    lre = wave_sum(lre);
-    lim = wave_sum(lim);
-    double ph = remainder(lim, 2.0 * M_PI);
-    if (ph <= -M_PI) ph += 2.0 * M_PI;
+    int e = 0;
+    (void)frexp(fmax(fabs(p.re), fabs(p.im)), &e);   // 0 for 0, inf and NaN: kept as they are
+    p = {ldexp(p.re, -e), ldexp(p.im, -e)};
+    p = p * dpp_c<0xB1>(p);    // quad_perm [1,0,3,2]
+    p = p * dpp_c<0x4E>(p);    // quad_perm [2,3,0,1]
+    p = p * dpp_c<0x124>(p);   // row_ror:4
+    p = p * dpp_c<0x128>(p);   // row_ror:8
+    const cd P = (readlane_c(p, 0) * readlane_c(p, 16)) * (readlane_c(p, 32) * readlane_c(p, 48));
+    const double E = wave_sum((double)e);            // exact: integers below 2^53
+    constexpr double LN2_HI = 0x1.62e42fefa3800p-1;  // ln 2 to 42 bits: E * LN2_HI exact for |E| < 2^11
+    constexpr double LN2_LO = 0x1.ef35793c76730p-45; // ln 2 - LN2_HI
+    const double lre = fma(E, LN2_HI, fma(E, LN2_LO, log(hypot(P.re, P.im))));
+    const double ph = atan2(P.im, P.re);
     *out_logdet = cd{lre, ph};
     if (!isfinite(lre) || !isfinite(ph)) return 2;
-    return (cos(ph) > 0.0) ? 0 : 1;
+    return (P.re > 0.0) ? 0 : 1;
 }
 
 }  // namespace df
