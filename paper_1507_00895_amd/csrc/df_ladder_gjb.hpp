@@ -84,12 +84,7 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = 
                 tp[r] = fma_c(tp[r], in ? pv[r] : cd{0.0, 0.0}, xj);
             }
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tp[r] = row16_sum(tp[r]);
-        if (lj == 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tv[16 * w + MT<double>::row(lg, r)] = tp[r];
-        }
+        rows16_sum<ITEMS == 1>(tp, sh.Xw[w], tv + 16 * w, tid);
     }
 
     // ---- D = 1 - gamma diag(chi) in accumulator tiles (opaque column index:
@@ -174,12 +169,7 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = 
                 yp[r] = fma_c(yp[r], cd{Cr[tc][r], Ci[tc][r]}, in ? gv[r] : cd{0.0, 0.0});
             }
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) yp[r] = row16_sum(yp[r]);
-        if (lj == 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) yv[16 * w + MT<double>::row(lg, r)] = yp[r];
-        }
+        rows16_sum<ITEMS == 1>(yp, sh.Xw[w], yv + 16 * w, tid);
     }
     __syncthreads();
     const int stt = s_flag;
