@@ -295,22 +295,56 @@ __device__ __forceinline__ double wave_sum(double x) {
     return (readlane_v(x, 0) + readlane_v(x, 16)) + (readlane_v(x, 32) + readlane_v(x, 48));
 }
 
+// Step 0 of the power steps (v = 1): the row sums of B over the wave's
+// block-row, each element |re| + |im| in the tiles' own precision (|.| is an
+// operand modifier there), accumulated in FP32.
+// DW, the wave's diagonal tile, is a compile-time constant here (the caller
+// dispatches on the wave-uniform block-row index), so only the four elements
+// per lane of that tile choose between the diagonal and off-diagonal forms.
+template <typename T, int NP, int DW>
+__device__ __forceinline__ void cert_rowsums0(const typename MT<T>::v4 (&Cr)[NP / 16],
+                                              const typename MT<T>::v4 (&Ci)[NP / 16], int lj,
+                                              int lg, float (&u)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) u[r] = 0.f;
+#pragma unroll
+    for (int tc = 0; tc < NP / 16; ++tc)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            T a = fabs(Cr[tc][r]);
+            if (tc == DW && lj == MT<T>::row(lg, r)) a = fabs(T(1) - Cr[tc][r]) + T(1e-6);
+            u[r] += (float)(a + fabs(Ci[tc][r]));
+        }
+}
+template <typename T, int NP, int K = 0>
+__device__ __forceinline__ void cert_rowsums0_at(int wu, const typename MT<T>::v4 (&Cr)[NP / 16],
+                                                 const typename MT<T>::v4 (&Ci)[NP / 16], int lj,
+                                                 int lg, float (&u)[4]) {
+    if constexpr (K + 1 < NP / 16) {
+        if (wu == K) cert_rowsums0<T, NP, K>(Cr, Ci, lj, lg, u);
+        else cert_rowsums0_at<T, NP, K + 1>(wu, Cr, Ci, lj, lg, u);
+    } else {
+        cert_rowsums0<T, NP, K>(Cr, Ci, lj, lg, u);
+    }
+}
+
 // Collatz-Wielandt bound of rho(cabs1(M) + eps I), eps = 1e-6 (it keeps every
 // component of v positive and normal in FP32 over the steps taken, and
 // raises the bound by eps at most), for M = 1 - D; uniform result across the
 // work-group.  Power steps from v = 1; after each step the bound
 // max_i (B v)_i / v_i is formed and the loop stops as soon as it is below
-// `accept` (any positive v gives a valid bound).  The
-// arithmetic is FP32: every term is non-negative, so the computed sums are
-// within n * 2^-24 relative of the exact ones, and the bound is inflated by
-// (1 + 1e-5) to stay an upper bound.  Contains barriers: every thread must call.
+// `accept` (any positive v gives a valid bound).  The sums are FP32 (step 0
+// forms each element in the tiles' precision): every term is non-negative,
+// so the computed sums are within (n + 1) 2^-24 relative of the exact ones,
+// and the bound is inflated by (1 + 1e-5) to stay an upper bound.
+// Contains barriers: every thread must call.
 //
 // peers, n_peers: the states of all items of the work-group when it holds
 // several (one per slot of waves), else null.  Then the loop stops only when
 // every item's bound passes, so that all items take the same barriers; the
 // bound of an item that passed earlier keeps shrinking (the quotient of a
 // power step never rises).
-template <typename T, int NP>
+template <typename T, int NP, bool FAST0 = true>
 __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP / 16],
                                              const typename MT<T>::v4 (&Ci)[NP / 16],
                                              GjShared<T, NP> &sh, int iters, double accept,
@@ -318,30 +352,29 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
                                              int n_peers = 0) {
     constexpr int NT = NP / 16;
     const int w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
-    // step 0 starts from v = 1 without reading it (no barrier before it)
     double cw = INFINITY;
-    for (int it = 0; it < iters; ++it) {
-        const double *v = sh.vbuf[it & 1];
-        float u[4] = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (!FAST0) {
+        // step 0 starts from v = 1 without reading it (no barrier before it)
+        for (int it = 0; it < iters; ++it) {
+            const double *v = sh.vbuf[it & 1];
+            float u[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int tc = 0; tc < NT; ++tc) {
-            const int j = 16 * tc + lj;
-            const float vj = (it == 0) ? 1.0f : (float)v[j];
+            for (int tc = 0; tc < NT; ++tc) {
+                const int j = 16 * tc + lj;
+                const float vj = (it == 0) ? 1.0f : (float)v[j];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * w + MT<T>::row(lg, r);
-                const float mr = (float)(((i == j) ? T(1) : T(0)) - Cr[tc][r]);
-                const float b = fabsf(mr) + fabsf((float)Ci[tc][r]) + ((i == j) ? 1e-6f : 0.0f);
-                u[r] = fmaf(b, vj, u[r]);
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * w + MT<T>::row(lg, r);
+                    const float mr = (float)(((i == j) ? T(1) : T(0)) - Cr[tc][r]);
+                    const float b = fabsf(mr) + fabsf((float)Ci[tc][r]) + ((i == j) ? 1e-6f : 0.0f);
+                    u[r] = fmaf(b, vj, u[r]);
+                }
             }
-        }
-        // rows live in the 16 lanes of one DPP row (FP64 layout) or of one
-        // quarter (FP32 layout): either way one row of 16 lanes
+            // rows live in the 16 lanes of one DPP row (FP64 layout) or of one
+            // quarter (FP32 layout): either way one row of 16 lanes
 #pragma unroll
-        for (int r = 0; r < 4; ++r) u[r] = row16_sum(u[r]);
-        // from v = 1 the first bound is the largest row sum of B
-        const bool bound = true;
-        if (bound) {
+            for (int r = 0; r < 4; ++r) u[r] = row16_sum(u[r]);
+            // from v = 1 the first bound is the largest row sum of B
             float ratio = 0.f;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -351,13 +384,11 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
             }
             const double m = wave_max_pos((double)ratio);
             if (l == 0) sh.wmax[it & 1][w] = m;
-        }
-        if (lj == 0) {
+            if (lj == 0) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sh.vbuf[(it + 1) & 1][16 * w + MT<T>::row(lg, r)] = u[r];
-        }
-        __syncthreads();
-        if (bound) {
+                for (int r = 0; r < 4; ++r) sh.vbuf[(it + 1) & 1][16 * w + MT<T>::row(lg, r)] = u[r];
+            }
+            __syncthreads();
             double c = 0.0, co = 0.0;
             for (int x = 0; x < NT; ++x) c = sh.wmax[it & 1][x] > c ? sh.wmax[it & 1][x] : c;
             for (int k = 0; k < n_peers; ++k)
@@ -368,8 +399,66 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
             // uniform: every thread of the work-group read the same wmax
             if (cw < accept && co * (1.0 + 1e-5) < accept) break;
         }
+        return cw;
+    } else {
+        // u = B v over the wave's rows (row sums across the 16 lanes of a row),
+        // the wave's largest quotient u_i / v_i, the next v; then the block's bound
+        // after a barrier.  Returns true when the bound (and every peer's) passes.
+        auto finish = [&](int it, float (&u)[4], const double *v) __attribute__((always_inline)) {
+            // rows live in the 16 lanes of one DPP row (FP64 layout) or of one
+            // quarter (FP32 layout): either way one row of 16 lanes
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[r] = row16_sum(u[r]);
+            float ratio = 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // from v = 1 the first bound is the largest row sum of B
+                const float rr = v ? u[r] * __builtin_amdgcn_rcpf((float)v[16 * w + MT<T>::row(lg, r)]) : u[r];
+                ratio = rr > ratio ? rr : ratio;
+            }
+            const double m = wave_max_pos((double)ratio);
+            if (l == 0) sh.wmax[it & 1][w] = m;
+            if (lj == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sh.vbuf[(it + 1) & 1][16 * w + MT<T>::row(lg, r)] = u[r];
+            }
+            __syncthreads();
+            double c = 0.0, co = 0.0;
+            for (int x = 0; x < NT; ++x) c = sh.wmax[it & 1][x] > c ? sh.wmax[it & 1][x] : c;
+            for (int k = 0; k < n_peers; ++k)
+                for (int x = 0; x < NT; ++x)
+                    co = peers[k].wmax[it & 1][x] > co ? peers[k].wmax[it & 1][x] : co;
+            // rcpf is within 1 ulp; the factor covers it and the sums' rounding
+            cw = c * (1.0 + 1e-5);
+            // uniform: every thread of the work-group read the same wmax
+            return cw < accept && co * (1.0 + 1e-5) < accept;
+        };
+        // step 0 from v = 1, without reading it (no barrier before it), by
+        // cert_rowsums0
+        {
+            float u[4];
+            cert_rowsums0_at<T, NP>(__builtin_amdgcn_readfirstlane(w), Cr, Ci, lj, lg, u);
+            if (finish(0, u, nullptr)) return cw;
+        }
+        for (int it = 1; it < iters; ++it) {
+            const double *v = sh.vbuf[it & 1];
+            float u[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int tc = 0; tc < NT; ++tc) {
+                const int j = 16 * tc + lj;
+                const float vj = (float)v[j];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 16 * w + MT<T>::row(lg, r);
+                    const float mr = (float)(((i == j) ? T(1) : T(0)) - Cr[tc][r]);
+                    const float b = fabsf(mr) + fabsf((float)Ci[tc][r]) + ((i == j) ? 1e-6f : 0.0f);
+                    u[r] = fmaf(b, vj, u[r]);
+                }
+            }
+            if (finish(it, u, v)) break;
+        }
+        return cw;
     }
-    return cw;
 }
 
 // Invert one 16 x 16 complex tile in place, held by one wave in the MFMA
@@ -389,6 +478,12 @@ __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename 
     typedef cplx<T> ct;
     const int l = tid & 63, lj = l & 15, lg = l >> 4;
     cd pvl = {0.0, 0.0};   // FP64: lane s < 16 collects the pivot of step s
+    // the high word of 1 on the lanes of the pivot column (lj == s), else 0;
+    // rotated one lane along the row after each step (row_ror:1: lane lj
+    // takes the value of lane lj - 1 mod 16), instead of a compare and select
+    // per step
+    constexpr int ONE_HI = sizeof(T) == 8 ? 0x3ff00000 : 0x3f800000;
+    int one_hi = (lj == 0) ? ONE_HI : 0;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         const int ls = MT<T>::lg_of(s), rs = MT<T>::r_of(s);
@@ -407,7 +502,11 @@ __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename 
         for (int r = 0; r < 4; ++r) c[r] = {row_bcast_v(Xr[r], s), row_bcast_v(Xi[r], s)};
         const ct ip = recip_fast(piv);
         // r'_j = r_j / p; on the pivot column r_s = p, and (r_s + 1) / p = 1 + 1/p
-        const ct rp = ct{rr.re + ((lj == s) ? T(1) : T(0)), rr.im} * ip;
+        T one_s;
+        if constexpr (sizeof(T) == 8) one_s = __hiloint2double(one_hi, 0);
+        else one_s = __int_as_float(one_hi);
+        const ct rp = ct{rr.re + one_s, rr.im} * ip;
+        one_hi = __builtin_amdgcn_mov_dpp(one_hi, 0x121, 0xf, 0xf, false);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             ct cf = c[r];

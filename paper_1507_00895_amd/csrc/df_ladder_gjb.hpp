@@ -109,7 +109,7 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = 
         }
     }
 
-    const double cw = gj_certify<double, NP>(Cr, Ci, sh, CERT_ITERS, CERT_MAX_F64, tid,
+    const double cw = gj_certify<double, NP, (NP <= 64)>(Cr, Ci, sh, CERT_ITERS, CERT_MAX_F64, tid,
                                              ITEMS > 1 ? shv : nullptr, ITEMS > 1 ? ITEMS : 0);
     bool skip = dummy;   // no results of this half are written
     if (!(cw < CERT_MAX_F64)) {
