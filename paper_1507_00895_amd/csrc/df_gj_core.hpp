@@ -248,43 +248,48 @@ __device__ __forceinline__ double row16_sum(double x) {
 }
 __device__ __forceinline__ cd row16_sum(cd x) { return {row16_sum(x.re), row16_sum(x.im)}; }
 __device__ __forceinline__ cf row16_sum(cf x) { return {row16_sum(x.re), row16_sum(x.im)}; }
-// Row sums of a 16-row block held one column per lane, FP64: v[r] is the
-// lane's partial sum of row MT<double>::row(lg, r) (its column lj); the 16
-// sums go to out[0..15].  The partials pass through the wave's own LDS block
+// Row sums of a 16-row block held one column per lane: v[r] is the lane's
+// partial sum of row MT<T>::row(lg, r) (its column lj); the 16 sums go to
+// out[0..15] (FP64).  The partials pass through the wave's own LDS block
 // buf (16 x 17, free outside the sweep) and each pair of lanes adds one part
-// of one row, so the reduction takes a dozen vector instructions per lane
-// where reducing the eight doubles by DPP across the 16 lanes took 96.
-// Wave-local: no barrier; out is read after the caller's next barrier.
-__device__ __forceinline__ void rows16_sum_lds(const cd (&v)[4], cd (*buf)[17], cd *out, int tid) {
+// of one row, so the reduction takes about a dozen vector instructions per
+// lane where reducing the eight values by DPP across the 16 lanes took 96
+// (FP64) or 32 (FP32).  Wave-local: no barrier; out is read after the
+// caller's next barrier.
+template <typename T>
+__device__ __forceinline__ void rows16_sum_lds(const cplx<T> (&v)[4], cplx<T> (*buf)[17], cd *out,
+                                               int tid) {
     const int l = tid & 63, lj = l & 15, lg = l >> 4;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) put_split<double>(buf[MT<double>::row(lg, r)][lj], v[r].re, v[r].im);
+    for (int r = 0; r < 4; ++r) put_split<T>(buf[MT<T>::row(lg, r)][lj], v[r].re, v[r].im);
     wave_sync_lds();
     // lane l: row i = l >> 2, part (l >> 1) & 1 (re, im), columns 8 h .. 8 h + 7
     const int h = l & 1, part = (l >> 1) & 1, i = l >> 2;
-    const double *src = &buf[i][8 * h].re + part;
-    double acc = src[0];
+    const T *src = &buf[i][8 * h].re + part;
+    T acc = src[0];
 #pragma unroll
     for (int k = 1; k < 8; ++k) acc += src[2 * k];
-    acc += dpp_d<0xB1>(acc);   // quad_perm [1,0,3,2]: the other half of the row
-    if (h == 0) (&out[i].re)[part] = acc;
+    // quad_perm [1,0,3,2]: the other half of the row
+    if constexpr (sizeof(T) == 8) acc += dpp_d<0xB1>(acc);
+    else acc += dpp_f<0xB1>(acc);
+    if (h == 0) (&out[i].re)[part] = (double)acc;
     // (this wave's later writes to buf follow its reads: LDS operations of
     // one wave complete in order)
 }
 // The same sums, through LDS (LDS_SUMS) or by DPP across the lanes (fewer
-// registers: the two-item build at NP = 96, held to 168 VGPRs, spilled more
-// with the LDS path and measured 0.7 % slower).
-template <bool LDS_SUMS>
-__device__ __forceinline__ void rows16_sum(cd (&v)[4], cd (*buf)[17], cd *out, int tid) {
+// registers: the two-item builds at NP = 96, held to 168 VGPRs, spilled more
+// with the LDS path, and the FP64 one measured 0.7 % slower).
+template <bool LDS_SUMS, typename T>
+__device__ __forceinline__ void rows16_sum(cplx<T> (&v)[4], cplx<T> (*buf)[17], cd *out, int tid) {
     if constexpr (LDS_SUMS) {
-        rows16_sum_lds(v, buf, out, tid);
+        rows16_sum_lds<T>(v, buf, out, tid);
     } else {
         const int l = tid & 63, lj = l & 15, lg = l >> 4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = row16_sum(v[r]);
         if (lj == 0) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[MT<double>::row(lg, r)] = v[r];
+            for (int r = 0; r < 4; ++r) out[MT<T>::row(lg, r)] = cd{(double)v[r].re, (double)v[r].im};
         }
     }
 }

@@ -131,12 +131,9 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem, bool dummy 
                 tf[r] = fma_c(tf[r], in ? cf{gv[r].z, gv[r].w} : cf{0.f, 0.f}, xj);
             }
         }
-        // the row sums in FP32 too (the FP32 ladder's own error is far larger)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const cf ts = row16_sum(tf[r]);
-            tp[r] = {(double)ts.re, (double)ts.im};
-        }
+        // the row sums in FP32 too (the FP32 ladder's own error is far larger),
+        // through the wave's LDS block (free before the sweep) in the one-item builds
+        rows16_sum<ITEMS == 1>(tf, sh.gj.Xw[w], tv + 16 * w, tid);
     } else {
     // t first, on its own, so that its loads do not sit beside the D tiles
 #pragma unroll
@@ -174,10 +171,10 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem, bool dummy 
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) tp[r] = row16_sum(tp[r]);
-    }
     if (lj == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) tv[16 * w + MT<float>::row(lg, r)] = tp[r];
+    }
     }
 
     // The refined kernel keeps items whose bound is below CERT_NEAR_MIXED; the
@@ -249,16 +246,9 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem, bool dummy 
                                   in ? cf{gv[r].x, gv[r].y} : cf{0.f, 0.f});
                 }
             }
-            cd yp[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const cf ys = row16_sum(yf[r]);
-                yp[r] = {(double)ys.re, (double)ys.im};
-            }
-            if (lj == 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) ypart[16 * w + MT<float>::row(lg, r)] = yp[r];
-            }
+            // row sums through the wave's LDS block (the sweep is over) in the
+            // one-item builds
+            rows16_sum<ITEMS == 1>(yf, sh.gj.Xw[w], ypart + 16 * w, tid);
         }
         __syncthreads();
         const int stt = s_flag;
