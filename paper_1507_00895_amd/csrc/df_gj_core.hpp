@@ -211,6 +211,11 @@ template <typename T> __device__ __forceinline__ void put_split(cplx<T> &d, T re
 
 template <typename T, int NP> struct GjShared {
     static constexpr int NT = NP / 16;
+    // vbuf seen as complex entries, where the tile inversions' lanes without
+    // the pivot put their element (vbuf is used by the certificate alone,
+    // before the sweep, and written there before it is read)
+    static constexpr int DUMP_N = NP >= 64 ? 64 : (NP >= 32 ? 32 : 16);
+    __device__ __forceinline__ cd *dump() { return reinterpret_cast<cd *>(&vbuf[0][0]); }
     cplx<T> Rb[16][NP];          // old block-row of the current tile column
     cplx<T> Xw[NT][16][17];      // per-wave layout exchange (accumulator -> operand)
     cd pivv[NP];                 // scalar pivots, FP64
@@ -477,12 +482,12 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
 // where p is the pivot, r_j = x_sj and c_i = x_is: this yields x_ij - c_i r_j / p
 // off the pivot row and column, r_j / p on the pivot row, -c_i / p on the
 // pivot column and 1/p at the pivot, i.e. the in-place Gauss-Jordan step.
-template <typename T>
+template <typename T, int DUMP_N>
 __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename MT<T>::v4 &Xi,
-                                               cd *pivrow, int tid) {
+                                               cd *pivrow, cd *dump, int tid) {
+    static_assert((DUMP_N & (DUMP_N - 1)) == 0, "dump entries: a power of two");
     typedef cplx<T> ct;
     const int l = tid & 63, lj = l & 15, lg = l >> 4;
-    cd pvl = {0.0, 0.0};   // FP64: lane s < 16 collects the pivot of step s
     // the high word of 1 on the lanes of the pivot column (lj == s), else 0;
     // rotated one lane along the row after each step (row_ror:1: lane lj
     // takes the value of lane lj - 1 mod 16), instead of a compare and select
@@ -494,11 +499,16 @@ __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename 
         const int ls = MT<T>::lg_of(s), rs = MT<T>::r_of(s);
         const int src = s + 16 * ls;
         const ct piv = {readlane_v(Xr[rs], src), readlane_v(Xi[rs], src)};
-        // FP32: the pivot goes to LDS from the lane that holds it, per step
-        // (measured faster there; in FP64 it costs registers, and the
-        // pivots are gathered in lanes and stored once)
-        if constexpr (sizeof(T) == 4) {
-            if (l == src) pivrow[s] = cd{(double)Xr[rs], (double)Xi[rs]};
+        // every lane stores its element of row rs per step, the lane that
+        // holds the pivot into pivrow[s] and the others into dump (free
+        // during the sweep): no branch per step, and no gathering of the
+        // pivots from the scalar registers into lanes (a select reads one
+        // scalar register at most, so that took four copies and four selects
+        // per step)
+        {
+            cd *dst = (l == src) ? pivrow + s : dump + (l & (DUMP_N - 1));
+            if constexpr (sizeof(T) == 4) *dst = cd{(double)Xr[rs], (double)Xi[rs]};
+            else put_split<double>(*dst, Xr[rs], Xi[rs]);
         }
         const int from = (lj + 16 * ls) << 2;
         const ct rr = {bperm_v(from, Xr[rs]), bperm_v(from, Xi[rs])};
@@ -520,12 +530,6 @@ __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename 
             Xr[r] = x.re;
             Xi[r] = x.im;
         }
-        if constexpr (sizeof(T) == 8) {
-            if (l == s) pvl = cd{(double)piv.re, (double)piv.im};
-        }
-    }
-    if constexpr (sizeof(T) == 8) {
-        if (l < 16) pivrow[l] = pvl;
     }
 }
 
@@ -576,7 +580,7 @@ __device__ __forceinline__ void gj_sweep_plain(typename MT<T>::v4 (&Cr)[NP / 16]
             }
             v4 &Xr = Cr[0];
             v4 &Xi = Ci[0];
-            gj_tile_invert<T>(Xr, Xi, sh.pivv + 16 * t, tid);
+            gj_tile_invert<T, GjShared<T, NP>::DUMP_N>(Xr, Xi, sh.pivv + 16 * t, sh.dump(), tid);
 #pragma unroll
             for (int r = 0; r < 4; ++r) put_split<T>(sh.Xw[t][MT<T>::row(lg, r)][lj], Xr[r], Xi[r]);
         } else {
@@ -710,7 +714,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
     const int w = tid >> 6, l = tid & 63, lj = l & 15, lg = l >> 4;
     if (w == 0) {
         inversion_priority<T, true>();
-        gj_tile_invert<T>(Cr[0], Ci[0], sh.pivv, tid);
+        gj_tile_invert<T, GjShared<T, NP>::DUMP_N>(Cr[0], Ci[0], sh.pivv, sh.dump(), tid);
         inversion_priority<T, false>();
     }
 #pragma unroll
@@ -794,7 +798,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                     update(1, 2);
                     __builtin_amdgcn_sched_barrier(0);
                     inversion_priority<T, true>();
-                    gj_tile_invert<T>(Cr[1], Ci[1], sh.pivv + 16 * (t + 1), tid);
+                    gj_tile_invert<T, GjShared<T, NP>::DUMP_N>(Cr[1], Ci[1], sh.pivv + 16 * (t + 1), sh.dump(), tid);
                     inversion_priority<T, false>();
                     update(2, NT);
                     interleave_mfma<12 * (NT - 2), 20>();
@@ -849,7 +853,7 @@ __device__ __forceinline__ void gj_sweep_lookahead(typename MT<T>::v4 (&Cr)[NP /
                     update(1, 2);
                     __builtin_amdgcn_sched_barrier(0);
                     inversion_priority<T, true>();
-                    gj_tile_invert<T>(Cr[1], Ci[1], sh.pivv + 16 * (t + 1), tid);
+                    gj_tile_invert<T, GjShared<T, NP>::DUMP_N>(Cr[1], Ci[1], sh.pivv + 16 * (t + 1), sh.dump(), tid);
                     inversion_priority<T, false>();
                     update(2, NT);
                     interleave_mfma<16 * (NT - 2), 28>();
