@@ -27,7 +27,7 @@ constexpr double CERT_MAX_F64 = 0.999;
 // carried through with its results discarded, and `dummy` marks a slot
 // without an item of its own (the last work-group of the launch), which
 // computes a copy of the last item and writes nothing.
-template <int NP, bool LOOP, bool FULL, int ITEMS = 1, bool YE = true>
+template <int NP, bool LOOP, bool FULL, int ITEMS = 1>
 __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = false) {
     constexpr int NT = NP / 16;
     typedef MT<double>::v4 d4;
@@ -137,17 +137,11 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = 
         }
     }
     // ---- Gamma_nn = sum_l (D^-1)_nl gamma_ln  (gamma^T read row-wise); loads
-    // per tile column without branches (clamped indices, padding masked).  YE:
-    // formed by every wave before the radius test is known (the result is
+    // per tile column without branches (clamped indices, padding masked).
+    // Formed by every wave before the radius test is known (the result is
     // used only inside the radius), so that waves 1.. form it while wave 0
-    // forms log det, and one barrier fewer; else only inside the radius,
-    // after the test (the four-wave build measured 1.6 % faster so)
-    bool need_y = true;
-    if constexpr (!YE) {
-        __syncthreads();
-        need_y = (s_flag == 0);
-    }
-    if (need_y) {
+    // forms log det, with one barrier fewer
+    {
         // an opaque copy of the row base keeps the compiler from sharing these
         // indices with the identical ones of the D build, which would hold them
         // in registers across the sweep
@@ -202,9 +196,9 @@ __device__ __forceinline__ void gjb_loop(const LadderArgs &a0) {
 // registers and spilled.)  FULL selects the mask-free build, for launches
 // whose instances all have n_nu equal to NP (LadderArgs::full); each kernel
 // holds one of the two paths, as one holding both needed more registers.
-#define DF_GJB_BODY(NP, LOOP, FULL, YE)                                         \
+#define DF_GJB_BODY(NP, LOOP, FULL)                                             \
     if constexpr (LOOP) gjb_loop<NP, FULL>(a0);                                 \
-    else gjb_item<NP, false, FULL, 1, YE>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
+    else gjb_item<NP, false, FULL>(a0, a0.item0 + xcd_item(blockIdx.x, gridDim.x));
 
 // Register budgets of the same kernel: the compiler's own (two work-groups
 // per CU at NP = 48, 64) and builds capped for three and four waves per SIMD
@@ -213,17 +207,17 @@ __device__ __forceinline__ void gjb_loop(const LadderArgs &a0) {
 // cap) serve queue launches and persistent grids.
 template <int NP, bool LOOP, bool FULL>
 __global__ __launch_bounds__(NP * 4) void k_ladder_gjb_f64(LadderArgs a0) {
-    DF_GJB_BODY(NP, LOOP, FULL, true)
+    DF_GJB_BODY(NP, LOOP, FULL)
 }
 template <int NP, bool LOOP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(3, 3)))
 void k_ladder_gjb_f64_o3(LadderArgs a0) {
-    DF_GJB_BODY(NP, LOOP, FULL, true)
+    DF_GJB_BODY(NP, LOOP, FULL)
 }
 template <int NP, bool FULL>
 __global__ __launch_bounds__(NP * 4) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ladder_gjb_f64_o4(LadderArgs a0) {
-    DF_GJB_BODY(NP, false, FULL, false)
+    DF_GJB_BODY(NP, false, FULL)
 }
 
 // K items per work-group: an item is NP / 16 waves, and with six-wave

@@ -65,7 +65,7 @@ template <int NP> struct PlainShared {
 // certified items.  FULL: n_nu equals the padded size NP (no clamped index,
 // no masked padding).  ITEMS = 2 (FP32 ladder alone): two items per
 // work-group, as in the FP64 kernel's two-item build (gjb_item).
-template <int NP, bool REFINE, bool FULL, int ITEMS = 1, bool YE = true>
+template <int NP, bool REFINE, bool FULL, int ITEMS = 1>
 __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem, bool dummy = false) {
     static_assert(ITEMS == 1 || !REFINE, "two items per work-group: FP32 ladder only");
     constexpr int NT = NP / 16;
@@ -212,15 +212,10 @@ __device__ __forceinline__ void mixed_item(LadderArgs a0, int gitem, bool dummy 
     }
 
     if constexpr (!REFINE) {
-        // YE: Gamma_nn formed by every wave before the radius test is known
-        // (used only inside the radius), while wave 0 forms log det, with one
-        // barrier fewer; else after the test, inside the radius only
-        bool need_y = true;
-        if constexpr (!YE) {
-            __syncthreads();
-            need_y = (s_flag == 0);
-        }
-        if (need_y) {
+        // Gamma_nn formed by every wave before the radius test is known (used
+        // only inside the radius), while wave 0 forms log det, with one
+        // barrier fewer
+        {
             // ---- Gamma_nn = sum_l X_nl gamma_ln  (gamma^T read row-wise); loads
             // per tile column without branches.  Opaque copies of the row and
             // column bases keep the compiler from sharing these indices with
