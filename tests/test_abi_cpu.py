@@ -117,6 +117,10 @@ def test_workspace_size_and_validation_order():
     bad = B.make_opts(symmetry=2)
     assert lib.df_ladder_solve(arr, 1, ctypes.byref(bad), 0x1000, n.value, None) == B.DF_E_INVAL
     assert lib.df_iterate(arr, 1, ctypes.byref(bad), None, None, 0x1000, n.value, None) == B.DF_E_INVAL
+    # iterations per captured graph: 0 or 1 (one), up to 64
+    for u in (-1, 65):
+        bad = B.make_opts(graph_unroll=u)
+        assert lib.df_iterate(arr, 1, ctypes.byref(bad), None, None, 0x1000, n.value, None) == B.DF_E_INVAL
     # Anderson history needs workspace
     m0, m5 = ctypes.c_size_t(0), ctypes.c_size_t(0)
     assert lib.df_workspace_size(arr, 1, ctypes.byref(B.make_opts()), ctypes.byref(m0)) == B.DF_OK
