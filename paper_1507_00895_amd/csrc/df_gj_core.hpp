@@ -215,7 +215,11 @@ template <typename T, int NP> struct GjShared {
     // the pivot put their element (vbuf is used by the certificate alone,
     // before the sweep, and written there before it is read)
     static constexpr int DUMP_N = NP >= 64 ? 64 : (NP >= 32 ? 32 : 16);
-    __device__ __forceinline__ cd *dump() { return reinterpret_cast<cd *>(&vbuf[0][0]); }
+    __device__ __forceinline__ cd *dump() {
+        static_assert(offsetof(GjShared, vbuf) % alignof(cd) == 0, "vbuf holds complex entries");
+        static_assert(sizeof(vbuf) >= DUMP_N * sizeof(cd), "vbuf holds DUMP_N complex entries");
+        return reinterpret_cast<cd *>(&vbuf[0][0]);
+    }
     cplx<T> Rb[16][NP];          // old block-row of the current tile column
     cplx<T> Xw[NT][16][17];      // per-wave layout exchange (accumulator -> operand)
     cd pivv[NP];                 // scalar pivots, FP64
