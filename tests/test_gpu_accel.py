@@ -88,3 +88,19 @@ def test_accelerated_adaptive_reaches_fp64_fixed_point(B):
     assert max(d) < 1e-11
     for a, b in zip(ad, f64):
         assert rel(a.sigma.cpu().numpy(), b.sigma.cpu().numpy()) <= 1e-9
+
+
+@pytest.mark.parametrize("accel", [0, 5], ids=["linear", "anderson"])
+def test_adaptive_fixed_point_matches_oracle(B, accel):
+    """The adaptive loop (FP32 ladders until the diff falls below switch_tol,
+    FP64 ladders from then on), with linear mixing or Anderson acceleration,
+    against the oracle's plain FP64 loop (eq. dyson and the ladder of Sec. 2.2
+    iterated to a diff below 1e-12) on the small 2D workload: the same fixed
+    point to 1e-10."""
+    p = I.workload_small()[0]
+    r = O.iterate(p.g, p.delta, p.eps, p.gamma_uu, p.gamma_ud, p.D, p.nk, p.beta, p.n_om,
+                  alpha=0.5, tol=1e-12, max_iter=400)
+    insts, iters, d = _run(B, [p], prec=B.DF_ADAPTIVE, mix=0.5, tol=1e-12, max_iter=400,
+                           accel=accel, switch_tol=1e-5)
+    assert d[0] < 1e-12
+    assert rel(insts[0].sigma.cpu().numpy(), r.sigma) <= 1e-10
