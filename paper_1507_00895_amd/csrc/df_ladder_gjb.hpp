@@ -120,8 +120,9 @@ __device__ __forceinline__ void gjb_item(LadderArgs a0, int gitem, bool dummy = 
 
     // look-ahead inversion up to NP = 96: at 96 it removes the spills (7.14 ->
     // 6.76 ms per instance), at 32 / 48 / 64 the fastest builds gain 2 / 3 / 1 %
-    // now that t is formed before the D tiles; at 128 it measured even
-    gj_sweep<double, NP, (NP != 128)>(Cr, Ci, sh, tid);
+    // now that t is formed before the D tiles; at 128 the persistent (LOOP)
+    // build gains 1.7 % with it and the one-item build loses 1.2 %
+    gj_sweep<double, NP, (NP != 128) || LOOP>(Cr, Ci, sh, tid);
 
     if (w == 0) {
         cd ldv;
