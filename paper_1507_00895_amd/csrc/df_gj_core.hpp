@@ -23,7 +23,8 @@
 // wave applies A_w,c += G_w A_t,c (c != t) with G_t = A_tt^-1 - 1 and sets
 // tile (w, t) to G_w (A_tt^-1 for w = t).  This is the block form of the
 // in-place sweep: afterwards the tiles hold D^-1, and the scalar pivots
-// (stored in FP64) multiply to det D.
+// (stored in the tiles' precision; their product is formed in FP64)
+// multiply to det D.
 //
 // Every function takes the thread index as an argument: the kernels pass an
 // opaque copy made per item, so that nothing derived from it is hoisted out
@@ -215,14 +216,14 @@ template <typename T, int NP> struct GjShared {
     // the pivot put their element (vbuf is used by the certificate alone,
     // before the sweep, and written there before it is read)
     static constexpr int DUMP_N = NP >= 64 ? 64 : (NP >= 32 ? 32 : 16);
-    __device__ __forceinline__ cd *dump() {
-        static_assert(offsetof(GjShared, vbuf) % alignof(cd) == 0, "vbuf holds complex entries");
-        static_assert(sizeof(vbuf) >= DUMP_N * sizeof(cd), "vbuf holds DUMP_N complex entries");
-        return reinterpret_cast<cd *>(&vbuf[0][0]);
+    __device__ __forceinline__ cplx<T> *dump() {
+        static_assert(offsetof(GjShared, vbuf) % alignof(cplx<T>) == 0, "vbuf holds complex entries");
+        static_assert(sizeof(vbuf) >= DUMP_N * sizeof(cplx<T>), "vbuf holds DUMP_N complex entries");
+        return reinterpret_cast<cplx<T> *>(&vbuf[0][0]);
     }
     cplx<T> Rb[16][NP];          // old block-row of the current tile column
     cplx<T> Xw[NT][16][17];      // per-wave layout exchange (accumulator -> operand)
-    cd pivv[NP];                 // scalar pivots, FP64
+    cplx<T> pivv[NP];            // scalar pivots, in the tiles' precision
     double vbuf[2][NP];          // power-iteration vectors
     double wmax[2][NT];          // double-buffered: a wave may start the next step early
 };
@@ -488,7 +489,7 @@ __device__ __forceinline__ double gj_certify(const typename MT<T>::v4 (&Cr)[NP /
 // pivot column and 1/p at the pivot, i.e. the in-place Gauss-Jordan step.
 template <typename T, int DUMP_N>
 __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename MT<T>::v4 &Xi,
-                                               cd *pivrow, cd *dump, int tid) {
+                                               cplx<T> *pivrow, cplx<T> *dump, int tid) {
     static_assert((DUMP_N & (DUMP_N - 1)) == 0, "dump entries: a power of two");
     typedef cplx<T> ct;
     const int l = tid & 63, lj = l & 15, lg = l >> 4;
@@ -510,9 +511,8 @@ __device__ __forceinline__ void gj_tile_invert(typename MT<T>::v4 &Xr, typename 
         // scalar register at most, so that took four copies and four selects
         // per step)
         {
-            cd *dst = (l == src) ? pivrow + s : dump + (l & (DUMP_N - 1));
-            if constexpr (sizeof(T) == 4) *dst = cd{(double)Xr[rs], (double)Xi[rs]};
-            else put_split<double>(*dst, Xr[rs], Xi[rs]);
+            cplx<T> *dst = (l == src) ? pivrow + s : dump + (l & (DUMP_N - 1));
+            put_split<T>(*dst, Xr[rs], Xi[rs]);
         }
         const int from = (lj + 16 * ls) << 2;
         const ct rr = {bperm_v(from, Xr[rs]), bperm_v(from, Xi[rs])};
@@ -904,12 +904,13 @@ template <int CTRL> __device__ __forceinline__ cd dpp_c(cd v) {
 __device__ __forceinline__ cd readlane_c(cd v, int lane) {
     return {readlane_v(v.re, lane), readlane_v(v.im, lane)};
 }
-template <int NP>
-__device__ __forceinline__ int gj_logdet(const cd *pivv, cd *out_logdet, int tid) {
+template <int NP, typename T>
+__device__ __forceinline__ int gj_logdet(const cplx<T> *pivv, cd *out_logdet, int tid) {
     const int l = tid & 63;
-    cd p = (l < NP) ? pivv[l] : cd{1.0, 0.0};
+    auto piv = [&](int k) { return cd{(double)pivv[k].re, (double)pivv[k].im}; };
+    cd p = (l < NP) ? piv(l) : cd{1.0, 0.0};
     if constexpr (NP > 64) {
-        if (l + 64 < NP) p = p * pivv[l + 64];
+        if (l + 64 < NP) p = p * piv(l + 64);
     }
     int e = 0;
     (void)frexp(fmax(fabs(p.re), fabs(p.im)), &e);   // 0 for 0, inf and NaN: kept as they are
